@@ -1,0 +1,242 @@
+/*
+ * best.h - C ABI of the MI355X (gfx950) batched emulator posterior sampler.
+ *
+ * The library evaluates a dense tanh-MLP log-likelihood emulator and its gradient for
+ * thousands of chains at once and fuses it with the MH, MALA, HMC and AIES updates of
+ * "Posterior sampling in the Age of Emulators" (Sec. 2 and Sec. 3).  The target is
+ * declarative (struct best_problem):
+ *
+ *   log pi(x) = gauss_coef * G(phi(x)) + part(x) + offset        inside [lower, upper]
+ *             = -inf                                              outside (hard box)
+ *   G(y)      = -1/2 (y - m)^T P (y - m)
+ *   phi(x)    = x, except phi_v = x_v + beta((x_u - center)^2 - kappa) (twisted pair)
+ *   part(x)   = mlp_coef * MLP((x - in_center) * in_invscale)     plain_mode 0
+ *               the same inside [train_lo, train_hi], plain(x) outside plain_mode 1
+ *               plain(x) everywhere                                 plain_mode 2
+ *   MLP       h_0 = t, h_l = tanh(W_l h_{l-1} + b_l), out = w_out . h_L + b_out
+ *   plain(x)  chi^2 log-likelihood of a spectrum of damped cosines (struct best_plain_model)
+ *
+ * Every sampler except AIES runs in the whitened space of Sec. 2.2 / Algorithm 1:
+ * x = mu + L z with log pi_z(z) = log pi(mu + L z) + sum_i log L_ii, so HMC has the
+ * identity mass matrix.  The whitening (mu, L) is set by best_adapt (Sec. 3.2).
+ *
+ * Conventions for every call:
+ *   - Return value: BEST_OK (0) or a BEST_E* code; no exception crosses the ABI and the
+ *     library never aborts.  best_last_error(ctx) returns the message of the last failure
+ *     on that context (valid until the next call on it).
+ *   - Arrays of chain quantities are structure-of-arrays: element (i, c) of a [d][n]
+ *     array lives at index i * n + c (chain index fastest).
+ *   - Device pointers unless a flag says host.  The caller owns every pointer it passes;
+ *     the library copies what it keeps (the problem at best_init).
+ *   - Work is enqueued on the context's stream (best_config.stream, a hipStream_t, NULL
+ *     for the default stream).  Calls that return statistics synchronise that stream.
+ *   - One context is one stream and is not re-entrant; distinct contexts are independent.
+ *   - Precision (best_config.precision) applies to the hidden-layer GEMMs only; the
+ *     whitening, energies and Metropolis log-ratios are always computed in FP64.
+ */
+#ifndef BEST_H
+#define BEST_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define BEST_OK 0
+#define BEST_EINVAL 1  /* an argument is invalid (NULL, size, shape, option) */
+#define BEST_ENOMEM 2  /* a device or host allocation failed */
+#define BEST_EHIP 3    /* a HIP runtime call or kernel launch failed */
+#define BEST_ENOTPD 4  /* covariance not positive definite even after jitter */
+#define BEST_ESTATE 5  /* call not valid in the current state (e.g. AIES with odd n) */
+
+/* ---- precision of the hidden-layer GEMMs ---- */
+#define BEST_FP64 0 /* FP64 MFMA (v_mfma_f64_16x16x4) */
+#define BEST_FP32 1 /* FP32 MFMA (v_mfma_f32_16x16x4) */
+#define BEST_FP16 2 /* FP16 MFMA with FP32 accumulation */
+#define BEST_BF16 3 /* BF16 MFMA with FP32 accumulation */
+
+/* ---- samplers (Sec. 2) ---- */
+#define BEST_MH 0   /* random-walk Metropolis-Hastings in whitened space */
+#define BEST_MALA 1 /* Metropolis-adjusted Langevin, Sec. 2.1 */
+#define BEST_HMC 2  /* Hamiltonian Monte Carlo, leapfrog, identity mass (Sec. 2.1-2.2) */
+#define BEST_AIES 3 /* affine-invariant ensemble sampler, stretch move (Sec. 2.3) */
+
+/* ---- walker initialisation (Sec. 3.2) ---- */
+#define BEST_INIT_UNIFORM 0    /* uniform in the prior box */
+#define BEST_INIT_REPLICATED 1 /* every chain at init_point */
+#define BEST_INIT_GAUSSIAN 2   /* init_point + init_scale * L0 xi, xi ~ N(0, I) */
+
+/* ---- flags for best_logL_grad / best_get_state / best_set_state ---- */
+#define BEST_HOST_PTRS 1u /* the array arguments are host pointers */
+
+typedef struct best_ctx best_ctx;
+typedef struct best_trainer best_trainer;
+
+/* Plain forward model (the synthetic stand-in for an expensive likelihood pipeline):
+ *   t = (x - center) * invscale
+ *   S_j = sum_m exp(a_m . t) exp(-gamma0_m exp(g_m . t) xgrid_j)
+ *               cos(2 pi k_m xgrid_j + pi tanh(p_m . t))
+ *   plain(x) = -1/2 sum_j (S_j - data_j)^2 inv_sigma2_j
+ * a, g, p are [n_terms][d] row-major; k, gamma0 are [n_terms]; the rest [n_bins] / [d]. */
+typedef struct {
+  int32_t n_bins, n_terms;
+  const double *xgrid, *data, *inv_sigma2;
+  const double *a, *g, *p;
+  const double *k, *gamma0;
+  const double *center, *invscale;
+} best_plain_model;
+
+/* The target (see the top of this file).  All pointers are host pointers; the problem is
+ * deep-copied by best_init.  mlp_params is the flat vector
+ *   [W1 (H x d), b1 (H), W2 (H x H), b2, ..., W_L (H x H), b_L, w_out (H), b_out]
+ * of length best_mlp_nparams(d, width, n_hidden).  width must be a multiple of 64 and at
+ * most 2048; 1 <= d <= 32; 1 <= n_hidden <= 16. */
+typedef struct {
+  int32_t d;
+  const double *lower, *upper;
+  double gauss_coef;
+  const double *gauss_mean; /* [d] */
+  const double *gauss_prec; /* [d*d] row-major, symmetric */
+  int32_t twist_u, twist_v; /* twist_u < 0: no twist */
+  double twist_beta, twist_center, twist_kappa;
+  int32_t width, n_hidden;
+  const double *mlp_params;
+  const double *in_center, *in_invscale; /* [d] */
+  double mlp_coef, offset;
+  int32_t plain_mode; /* 0, 1 or 2 (see top) */
+  const double *train_lo, *train_hi; /* [d], plain_mode 1 only */
+  const best_plain_model *plain;     /* plain_mode 1 or 2 */
+} best_problem;
+
+typedef struct {
+  int64_t n_chains;          /* >= 1 (AIES needs an even count) */
+  int32_t precision;         /* BEST_FP64 / FP32 / FP16 / BF16 */
+  uint64_t seed;             /* Philox key */
+  int32_t init;              /* BEST_INIT_* */
+  const double *init_point;  /* [d] host, NULL = box centre */
+  double init_scale;         /* BEST_INIT_GAUSSIAN scale */
+  void *stream;              /* hipStream_t or NULL */
+  int32_t chains_per_block;  /* 0 = automatic, else 16, 32 or 64 */
+} best_config;
+
+/* Per-call sampler options. */
+typedef struct {
+  double eps;             /* MALA / HMC step size (whitened units); <= 0: use the
+                             context's current step size (dual-averaging result) */
+  double mh_scale;        /* MH proposal scale in whitened units (e.g. 2.4/sqrt(d)) */
+  double stretch_a;       /* AIES stretch parameter a > 1 (2 in the paper) */
+  int32_t n_leapfrog;     /* HMC leapfrog steps per trajectory (>= 1) */
+  int32_t thin;           /* record every thin-th step (>= 1) */
+  float *record;          /* device [record_capacity][d][n_chains] x-space samples or NULL */
+  int64_t record_capacity;
+  int32_t adapt_eps;      /* 1: dual-averaging update of the step size after every step */
+  double target_accept;   /* dual-averaging target (e.g. 0.57 MALA, 0.8 HMC) */
+} best_step_params;
+
+typedef struct {
+  int64_t accepted;        /* accepted transitions summed over chains and steps */
+  int64_t evals;           /* emulator evaluations (logL or logL+grad) */
+  int64_t n_nonfinite;     /* proposals whose log pi was NaN (rejected) */
+  int64_t n_oob;           /* proposals outside the prior box (rejected) */
+  int64_t n_recorded;      /* record slots written */
+  double sum_accept_prob;  /* sum of min(1, alpha) */
+  double ms;               /* wall time of the call's kernels (hipEvents) */
+  double eps;              /* current step size after the call */
+  double eps_bar;          /* dual-averaging averaged step size */
+} best_step_stats;
+
+typedef struct {
+  const float *samples;  /* device [n_samples][d][n_chains] window, NULL = current x */
+  int64_t n_samples;
+  int32_t update_mean;   /* 1: mu <- ensemble mean, 0: keep mu */
+  int32_t reset_da;      /* 1: restart dual averaging from the current step size */
+  int32_t finalize_da;   /* 1: step size <- dual-averaging average */
+  double target_accept;  /* for reset_da */
+} best_adapt_params;
+
+typedef struct {
+  double jitter;  /* lambda * mean(diag Sigma) added to the diagonal (0 if none) */
+  double logdet;  /* sum_i log L_ii of the new whitening */
+  double eps;     /* step size after the call */
+} best_adapt_info;
+
+/* ---- lifetime ---- */
+
+/* Validate and copy the problem, allocate device state, initialise the walkers
+ * (uniform / replicated / Gaussian; Sec. 3.2), set the initial whitening mu = box centre,
+ * L = diag(0.1 (upper - lower)) (Sec. 4: a diagonal covariance scaled to the box), and
+ * evaluate log pi and its gradient at the start.  *out is NULL on failure. */
+int best_init(best_ctx **out, const best_problem *p, const best_config *c);
+void best_destroy(best_ctx *h); /* NULL is a no-op; frees every library buffer */
+const char *best_strerror(int code);
+const char *best_last_error(const best_ctx *h);
+int64_t best_mlp_nparams(int32_t d, int32_t width, int32_t n_hidden);
+
+/* ---- the hot path ---- */
+
+/* Batch evaluation of log pi(x) and grad_x log pi(x) at n points x ([d][n]).  grad may be
+ * NULL (logL only).  Device pointers, or host pointers with BEST_HOST_PTRS (then the call
+ * synchronises).  The prior box applies (-inf outside; the gradient returned there is that
+ * of the unbounded expression). */
+int best_logL_grad(best_ctx *h, const double *x, int64_t n, double *logL, double *grad,
+                   uint32_t flags);
+
+/* Advance every chain n_steps transitions of `sampler` (BEST_MH / MALA / HMC / AIES).
+ * Randomness: Philox4x32-10 keyed by the seed, counter = (chain, global step,
+ * stream << 24 | substep, block); the global step counter advances by n_steps.
+ * out (may be NULL) receives the call's statistics; the call synchronises the stream. */
+int best_step(best_ctx *h, int32_t sampler, int64_t n_steps, const best_step_params *p,
+              best_step_stats *out);
+
+/* Covariance adaptation (Sec. 3.2): FP64 mean and covariance of the window (or of the
+ * current ensemble), symmetrised, Cholesky with jitter escalation (lambda = 1e-10 ...
+ * 1e-2 of the mean diagonal), new whitening (mu, L); every chain is re-whitened.  On
+ * BEST_ENOTPD the previous whitening is kept.  Also resets / finalises dual averaging. */
+int best_adapt(best_ctx *h, const best_adapt_params *p, best_adapt_info *out);
+
+/* ---- state, whitening, diagnostics ---- */
+int best_get_state(best_ctx *h, double *x, double *logL, double *grad, uint32_t flags);
+int best_set_state(best_ctx *h, const double *x, uint32_t flags); /* re-evaluates */
+int best_get_whitening(best_ctx *h, double *mu, double *L);       /* host, [d], [d*d] */
+int best_set_whitening(best_ctx *h, const double *mu, const double *L);
+uint64_t best_get_step_counter(const best_ctx *h);
+int best_set_step_counter(best_ctx *h, uint64_t step);
+int best_set_step_size(best_ctx *h, double eps);
+/* Replace the MLP weights (flat host vector, same layout as best_problem.mlp_params). */
+int best_set_mlp(best_ctx *h, const double *params, double mlp_coef, double offset);
+
+/* Multi-chain effective sample size of a record ([T][d][n_chains] device floats) per
+ * parameter: rho_t = 1 - (W - mean_m gamma_{m,t}) / var+, Geyer initial monotone
+ * sequence, ESS = M T / tau.  Autocovariances are summed directly on the device in FP64.
+ * ess_out: host [d]. */
+int best_ess(best_ctx *h, const float *record, int64_t T, double *ess_out);
+
+/* ---- learned emulator (training on plain-model pairs) ---- */
+
+/* A trainer owns an FP64 master copy of the MLP parameters and Adam moments on the device.
+ * Training minimises mean_c (MLP(t_c) - y_c)^2 with Adam (b1 0.9, b2 0.999, eps 1e-8). */
+int best_trainer_create(best_trainer **out, int32_t d, int32_t width, int32_t n_hidden,
+                        const double *init_params, int32_t precision, void *stream);
+void best_trainer_destroy(best_trainer *t);
+/* One epoch over perm ([n] device int32): batch i = perm[iB .. (i+1)B), ragged tail dropped.
+ * t_in: device [n][d] normalised inputs (FP32), y: device [n] standardised targets (FP32).
+ * The learning rate follows lr1 + (lr0 - lr1)(1 + cos(pi s / total_steps)) / 2 at Adam
+ * step s (counted from step0).  mean_loss (host, may be NULL) receives the epoch mean of
+ * the minibatch losses (synchronises). */
+int best_train_epoch(best_trainer *t, const float *t_in, const float *y, int64_t n,
+                     const int32_t *perm, int32_t batch, double lr0, double lr1,
+                     int64_t step0, int64_t total_steps, double *mean_loss);
+/* Gradient of the minibatch loss at the current parameters (no update); grad: host
+ * [nparams] FP64; loss: host. */
+int best_train_grad(best_trainer *t, const float *t_in, const float *y, int64_t batch,
+                    double *grad, double *loss);
+int best_trainer_get_params(best_trainer *t, double *out); /* host [nparams] */
+const char *best_trainer_last_error(const best_trainer *t);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BEST_H */

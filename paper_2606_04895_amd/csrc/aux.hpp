@@ -1,0 +1,42 @@
+// Host-visible launchers of the library's kernels.  Each is defined in the translation
+// unit that defines the kernel it launches.
+#pragma once
+#include "train.hpp"
+
+namespace best {
+
+constexpr int kEssTS = 64;   // time-window rows per autocovariance pass
+constexpr int kEssLB = 128;  // lags per autocovariance pass
+
+// Templated per precision (kernels_<prec>.hip).
+hipError_t launch_step(int prec, int MT, const KArgs& a, int grid, size_t lds, hipStream_t s);
+hipError_t launch_eval(int prec, int MT, const KArgs& a, int grid, size_t lds, hipStream_t s);
+hipError_t launch_pack(int prec, const double* flat, int d, int H, int nh, void* wf, void* wb,
+                       void* w1, void* bias, void* wout, hipStream_t s);
+hipError_t launch_train_tile(int prec, int MT, const TrainArgs& a, int grid, size_t lds,
+                             hipStream_t s);
+
+// kernels_aux.hip
+hipError_t launch_init_positions(const Target& tg, const State& S, const Rng& rng, int mode,
+                                 const double* pt, double scale, const double* L0,
+                                 hipStream_t s);
+hipError_t launch_rewhiten(const State& S, const Whiten& W, int d, hipStream_t s);
+hipError_t launch_da_update(const double* step_prob, int64_t N, double* da, hipStream_t s);
+hipError_t launch_stats(const State& S, int64_t* out_i, double* out_d, hipStream_t s);
+hipError_t launch_aies_record(const State& S, int d, float* rec, int64_t slot, int64_t pitch,
+                              hipStream_t s);
+hipError_t launch_moments(const float* rec, const double* xs, int64_t T, int64_t N,
+                          int64_t pitch, int d, const double* shift, double* part, int nblocks,
+                          int update_mean, double* mu, double* L, double* info, hipStream_t s);
+hipError_t launch_ess_chain_stats(const float* rec, int64_t T, int d, int64_t N, double* mean,
+                                  double* ssq, hipStream_t s);
+hipError_t launch_ess_autocov(const float* rec, const double* mean, int64_t T, int d,
+                              int64_t N, int64_t lag0, double* part, hipStream_t s);
+hipError_t launch_adam(double* p, double* m, double* v, const double* g, int64_t n, double lr,
+                       double b1, double b2, double eps, double c1, double c2, hipStream_t s);
+hipError_t launch_dw(const float* dl, const float* h, const float* th, const float* up,
+                     int64_t B, int d, int H, int nh, double* grad, const int64_t* offs,
+                     const int64_t* w_offs_host, hipStream_t s);
+hipError_t launch_sum(const double* part, int n, double scale, double* out, hipStream_t s);
+
+}  // namespace best

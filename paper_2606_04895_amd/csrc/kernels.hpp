@@ -1,0 +1,627 @@
+// Fused per-chain-tile kernels: target evaluation (FP64 assembly around the MLP emulator)
+// and the MH / MALA / HMC / AIES transitions.  Templated on the GEMM precision P and the
+// chain-tile width M = 16*MT; instantiated once per precision in kernels_<prec>.hip.
+#pragma once
+#include "mlp_tile.hpp"
+
+namespace best {
+
+constexpr int kMaxTerms = 8;  // plain model terms held in registers
+
+struct Target {
+  int d;
+  const double *lower, *upper;
+  double gauss_coef;
+  const double *gmean, *gprec;
+  int tw_u, tw_v;
+  double tw_beta, tw_center, tw_kappa;
+  const double *in_center, *in_invscale;
+  double mlp_coef, offset;
+  int plain_mode;
+  const double *train_lo, *train_hi;
+  int n_bins, n_terms;
+  const double *xgrid, *data, *w2, *pa, *pg, *pp, *pk, *pg0, *pc, *pis;
+};
+
+struct Whiten {
+  const double* mu;  // [d]
+  const double* L;   // [d*d] row-major lower triangle
+};
+
+// Chain state and per-chain scratch, SoA [d][Np] (chain fastest) and [Np].
+struct State {
+  int64_t Np, N;
+  double *x, *z, *gx, *lp;
+  double *xp, *zp, *gxp, *lpp, *q, *gz, *gzp;
+  uint32_t *n_acc, *n_nonfinite, *n_oob;
+  double *sum_prob, *step_prob;
+};
+
+// Byte offsets into dynamic LDS (computed on the host by lds_layout()).
+struct LdsLayout {
+  int big, th, gth, red, out, up, mi, md, total;
+};
+
+__host__ __device__ inline int align16(int v) { return (v + 15) & ~15; }
+
+// Union region: {2 activation buffers} during the MLP, {R, PR, plain results, plain
+// scratch} during the FP64 assembly.
+__host__ __device__ inline LdsLayout lds_layout(int M, int H, int d, int tsize, int vsize,
+                                               int asize) {
+  LdsLayout L;
+  const int mlp_bytes = 2 * M * H * tsize;
+  const int asm_bytes = 8 * (2 * d * M + M + M * d + kMaxD + 3 * kMaxTerms + kWaves * 32);
+  L.big = 0;
+  int o = align16(mlp_bytes > asm_bytes ? mlp_bytes : asm_bytes);
+  L.th = o;
+  o = align16(o + M * d * vsize);
+  L.gth = o;
+  o = align16(o + M * d * vsize);
+  L.red = o;
+  o = align16(o + kWaves * M * (d > 1 ? d : 1) * asize);
+  L.out = o;
+  o = align16(o + M * asize);
+  L.up = o;
+  o = align16(o + M * asize);
+  L.mi = o;  // ints: inbox[M], intrain[M], flag[M]
+  o = align16(o + 4 * M * 4);
+  L.md = o;  // doubles: 8 per chain
+  o = align16(o + 8 * M * 8);
+  L.total = o;
+  return L;
+}
+
+struct KArgs {
+  Target tg;
+  MlpParams mp;
+  Whiten wh;
+  State st;
+  Rng rng;
+  LdsLayout lds;
+  int sampler;
+  int64_t step0;
+  int n_steps;
+  double eps;
+  const double* eps_ptr;
+  double mh_scale, stretch_a;
+  int n_leap;
+  int thin;
+  float* record;
+  int64_t rec_cap, rec_s0, rec_pitch;  // rec_s0: index of the launch's first step in the call
+  int64_t n_tiles;
+  int64_t chain0;  // first chain of the launch (AIES half)
+  int aies_half;
+  void* hsave;
+  int64_t hsave_stride;  // elements of acc per workgroup
+  // best_logL_grad
+  const double* ex_x;
+  int64_t ex_pitch;
+  double *ex_lp, *ex_g;
+  int ex_grad;
+};
+
+// ---------------------------------------------------------------------------------------
+// Plain spectrum log-likelihood of one chain, computed by the whole workgroup.
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ void plain_chain(const Target& tg, const double* __restrict__ X, int64_t pitch,
+                            int64_t ch, bool grad, double* scratch, double* outv, double* outg) {
+  const int tid = threadIdx.x, d = tg.d, nt = tg.n_terms;
+  double* tpl = scratch;                  // [kMaxD]
+  double* A = tpl + kMaxD;                // [kMaxTerms]
+  double* gam = A + kMaxTerms;            // [kMaxTerms]
+  double* tht = gam + kMaxTerms;          // [kMaxTerms]
+  double* wred = tht + kMaxTerms;         // [kWaves][32]
+  if (tid < d) tpl[tid] = (X[tid * pitch + ch] - tg.pc[tid]) * tg.pis[tid];
+  __syncthreads();
+  if (tid < nt) {
+    double sa = 0, sg = 0, sp = 0;
+    for (int i = 0; i < d; ++i) {
+      sa += tg.pa[tid * d + i] * tpl[i];
+      sg += tg.pg[tid * d + i] * tpl[i];
+      sp += tg.pp[tid * d + i] * tpl[i];
+    }
+    A[tid] = exp(sa);
+    gam[tid] = tg.pg0[tid] * exp(sg);
+    tht[tid] = tanh(sp);
+  }
+  __syncthreads();
+  double ll = 0, sec[kMaxTerms], sxec[kMaxTerms], ses[kMaxTerms];
+#pragma unroll
+  for (int m = 0; m < kMaxTerms; ++m) sec[m] = sxec[m] = ses[m] = 0;
+  for (int j = tid; j < tg.n_bins; j += kThreads) {
+    const double xj = tg.xgrid[j];
+    double e[kMaxTerms], co[kMaxTerms], si[kMaxTerms], spec = 0;
+#pragma unroll
+    for (int m = 0; m < kMaxTerms; ++m) {
+      if (m < nt) {
+        e[m] = exp(-gam[m] * xj);
+        const double arg = 2.0 * 3.141592653589793 * tg.pk[m] * xj + 3.141592653589793 * tht[m];
+        sincos(arg, &si[m], &co[m]);
+        spec += A[m] * (e[m] * co[m]);
+      }
+    }
+    const double dr = spec - tg.data[j];
+    const double r = dr * tg.w2[j];
+    ll += dr * r;
+    if (grad) {
+#pragma unroll
+      for (int m = 0; m < kMaxTerms; ++m) {
+        if (m < nt) {
+          const double ec = e[m] * co[m];
+          sec[m] += r * ec;
+          sxec[m] += r * xj * ec;
+          ses[m] += r * (e[m] * si[m]);
+        }
+      }
+    }
+  }
+  const int lane = tid & 63, wv = tid >> 6;
+  ll = wave_sum(ll);
+  if (lane == 0) wred[wv * 32] = ll;
+  if (grad) {
+#pragma unroll
+    for (int m = 0; m < kMaxTerms; ++m) {
+      if (m < nt) {
+        const double a = wave_sum(sec[m]), b = wave_sum(sxec[m]), c = wave_sum(ses[m]);
+        if (lane == 0) {
+          wred[wv * 32 + 1 + m] = a;
+          wred[wv * 32 + 1 + kMaxTerms + m] = b;
+          wred[wv * 32 + 1 + 2 * kMaxTerms + m] = c;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double s = wred[0];
+    for (int w = 1; w < kWaves; ++w) s += wred[w * 32];
+    *outv = -0.5 * s;
+  }
+  if (grad && tid < d) {
+    double dt = 0;
+    for (int m = 0; m < nt; ++m) {
+      double s1 = 0, s2 = 0, s3 = 0;
+      for (int w = 0; w < kWaves; ++w) {
+        s1 += wred[w * 32 + 1 + m];
+        s2 += wred[w * 32 + 1 + kMaxTerms + m];
+        s3 += wred[w * 32 + 1 + 2 * kMaxTerms + m];
+      }
+      const double ca = s1 * A[m];
+      const double cg = -s2 * A[m] * gam[m];
+      const double cp = -s3 * A[m] * 3.141592653589793 * (1.0 - tht[m] * tht[m]);
+      dt += ca * tg.pa[m * d + tid] + cg * tg.pg[m * d + tid] + cp * tg.pp[m * d + tid];
+    }
+    outg[tid] = -dt * tg.pis[tid];
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------------------
+// Target evaluation for a tile of chains: LPo[c0+c] = log pi(x), GXo = grad_x log pi(x).
+// The inbox / intrain flags of every chain stay in LDS (mi) after the call.
+// ---------------------------------------------------------------------------------------
+template <class P, int MT>
+__device__ __forceinline__ void eval_tile(const KArgs& a, char* smem, typename P::acc* hsave,
+                          const double* __restrict__ X, int64_t pitch, int64_t c0, int mv,
+                          double* __restrict__ LPo, double* __restrict__ GXo, int64_t opitch,
+                          bool grad, bool box) {
+  using acc = typename P::acc;
+  using vec = typename P::vec;
+  constexpr int M = 16 * MT;
+  const Target& tg = a.tg;
+  const int tid = threadIdx.x, d = tg.d;
+  const LdsLayout& L = a.lds;
+  MlpSmem<P> s;
+  s.buf0 = (typename P::T*)(smem + L.big);
+  s.buf1 = s.buf0 + M * a.mp.H;
+  s.th = (vec*)(smem + L.th);
+  s.gth = (vec*)(smem + L.gth);
+  s.red = (acc*)(smem + L.red);
+  s.out = (acc*)(smem + L.out);
+  s.up = nullptr;
+  int* inbox = (int*)(smem + L.mi);
+  int* intrain = inbox + M;
+
+  for (int e = tid; e < M * d; e += kThreads) {
+    const int c = e / d, i = e % d;
+    const double xv = c < mv ? X[i * pitch + c0 + c] : tg.in_center[i];
+    s.th[e] = (vec)((xv - tg.in_center[i]) * tg.in_invscale[i]);
+  }
+  for (int c = tid; c < M; c += kThreads) {
+    int ib = 1, it = 1;
+    if (c < mv) {
+      for (int i = 0; i < d; ++i) {
+        const double xv = X[i * pitch + c0 + c];
+        ib &= (xv >= tg.lower[i]) & (xv <= tg.upper[i]);
+        if (tg.plain_mode == 1) it &= (xv >= tg.train_lo[i]) & (xv <= tg.train_hi[i]);
+      }
+    }
+    inbox[c] = ib;
+    intrain[c] = tg.plain_mode == 2 ? 0 : it;
+  }
+  __syncthreads();
+
+  if (tg.plain_mode != 2) {
+    mlp_forward<P, MT>(a.mp, s, hsave, nullptr);
+    if (grad) mlp_backward<P, MT>(a.mp, s, hsave, nullptr, true);
+  }
+
+  // FP64 assembly region (reuses the activation buffers)
+  double* R = (double*)(smem + L.big);
+  double* PR = R + d * M;
+  double* pv = PR + d * M;     // [M]
+  double* pgr = pv + M;        // [M][d]
+  double* psc = pgr + M * d;   // plain scratch
+  if (tg.plain_mode != 0) {
+    for (int c = 0; c < mv; ++c) {
+      if (!intrain[c]) plain_chain(tg, X, pitch, c0 + c, grad, psc, pv + c, pgr + c * d);
+    }
+  }
+  if (tg.gauss_coef != 0.0) {
+    for (int e = tid; e < d * M; e += kThreads) {
+      const int i = e / M, c = e % M;
+      double y = 0;
+      if (c < mv) {
+        y = X[i * pitch + c0 + c];
+        if (i == tg.tw_v) {
+          const double du = X[tg.tw_u * pitch + c0 + c] - tg.tw_center;
+          y = y + tg.tw_beta * (du * du - tg.tw_kappa);
+        }
+      }
+      R[e] = y - tg.gmean[i];
+    }
+    __syncthreads();
+    for (int e = tid; e < d * M; e += kThreads) {
+      const int i = e / M, c = e % M;
+      double v = 0;
+      for (int j = 0; j < d; ++j) v += tg.gprec[i * d + j] * R[j * M + c];
+      PR[e] = v;
+    }
+    __syncthreads();
+  }
+  if (tid < mv) {
+    const int c = tid;
+    double lp = tg.offset;
+    if (tg.gauss_coef != 0.0) {
+      double q = 0;
+      for (int i = 0; i < d; ++i) q += R[i * M + c] * PR[i * M + c];
+      lp += tg.gauss_coef * (-0.5 * q);
+    }
+    const bool use_mlp = tg.plain_mode == 0 || (tg.plain_mode == 1 && intrain[c]);
+    lp += use_mlp ? tg.mlp_coef * (double)s.out[c] : pv[c];
+    if (box && !inbox[c]) lp = -INFINITY;
+    LPo[c0 + c] = lp;
+  }
+  if (grad) {
+    for (int e = tid; e < d * M; e += kThreads) {
+      const int i = e / M, c = e % M;
+      if (c >= mv) continue;
+      double gi = 0;
+      if (tg.gauss_coef != 0.0) {
+        gi = -PR[e];
+        if (i == tg.tw_u) {
+          const double du = X[tg.tw_u * pitch + c0 + c] - tg.tw_center;
+          gi += -PR[tg.tw_v * M + c] * 2.0 * tg.tw_beta * du;
+        }
+        gi *= tg.gauss_coef;
+      }
+      const bool use_mlp = tg.plain_mode == 0 || (tg.plain_mode == 1 && intrain[c]);
+      gi += use_mlp ? tg.mlp_coef * (double)s.gth[c * d + i] * tg.in_invscale[i] : pgr[c * d + i];
+      GXo[i * opitch + c0 + c] = gi;
+    }
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------------------
+// Whitening helpers for a tile (thread per (i, c)); callers synchronise.
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ void tile_affine(const double* __restrict__ mu, const double* __restrict__ Lw,
+                                   int d, int M, int mv, const double* __restrict__ Z,
+                                   double* __restrict__ Xo, int64_t Np, int64_t c0) {
+  for (int e = threadIdx.x; e < d * M; e += kThreads) {
+    const int i = e / M, c = e % M;
+    if (c >= mv) continue;
+    double v = 0;
+    for (int j = 0; j <= i; ++j) v += Lw[i * d + j] * Z[j * Np + c0 + c];
+    Xo[i * Np + c0 + c] = mu[i] + v;
+  }
+}
+
+__device__ __forceinline__ double lt_dot(const double* __restrict__ Lw, int d, int i,
+                                const double* __restrict__ G, int64_t Np, int64_t ch) {
+  double v = 0;  // (L^T g)_i = sum_{j >= i} L[j][i] g_j
+  for (int j = i; j < d; ++j) v += Lw[j * d + i] * G[j * Np + ch];
+  return v;
+}
+
+__device__ __forceinline__ double accept_prob(double la) {
+  return isnan(la) ? 0.0 : exp(fmin(0.0, la));
+}
+
+// Accept bookkeeping for chain ch of the tile (called by one thread per chain).
+__device__ __forceinline__ bool decide(const KArgs& a, int64_t ch, uint64_t t, uint32_t sub, double la,
+                              double lpp, int inbox) {
+  const State& S = a.st;
+  const double u = accept_uniform(a.rng, ch, t, sub);
+  const bool acc = log(u) < la;
+  const double pr = accept_prob(la);
+  S.n_acc[ch] += acc ? 1u : 0u;
+  S.sum_prob[ch] += pr;
+  S.step_prob[ch] = pr;
+  S.n_nonfinite[ch] += isnan(lpp) ? 1u : 0u;
+  S.n_oob[ch] += inbox ? 0u : 1u;
+  return acc;
+}
+
+__device__ __forceinline__ void record_tile(const KArgs& a, int s, int d, int M, int mv, int64_t c0) {
+  const int64_t sc = a.rec_s0 + s + 1;
+  if (!a.record || (sc % a.thin) != 0) return;
+  const int64_t slot = sc / a.thin - 1;
+  if (slot >= a.rec_cap) return;
+  const State& S = a.st;
+  for (int e = threadIdx.x; e < d * M; e += kThreads) {
+    const int i = e / M, c = e % M;
+    if (c >= mv) continue;
+    a.record[(slot * d + i) * a.rec_pitch + c0 + c] = (float)S.x[i * S.Np + c0 + c];
+  }
+}
+
+// Copy proposal -> state for accepted chains (flag in LDS).
+__device__ __forceinline__ void commit_tile(const State& S, const int* flag, int d, int M, int mv,
+                                   int64_t c0, bool with_z, bool with_g) {
+  for (int e = threadIdx.x; e < d * M; e += kThreads) {
+    const int i = e / M, c = e % M;
+    if (c >= mv || !flag[c]) continue;
+    const int64_t o = i * S.Np + c0 + c;
+    S.x[o] = S.xp[o];
+    if (with_z) S.z[o] = S.zp[o];
+    if (with_g) S.gx[o] = S.gxp[o];
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Transitions for one tile at global step t.
+// ---------------------------------------------------------------------------------------
+template <class P, int MT>
+__device__ __forceinline__ void mh_tile(const KArgs& a, char* smem, typename P::acc* hsave, int64_t c0, int mv,
+                        uint64_t t) {
+  constexpr int M = 16 * MT;
+  const State& S = a.st;
+  const int d = a.tg.d, tid = threadIdx.x;
+  const int64_t Np = S.Np;
+  int* inbox = (int*)(smem + a.lds.mi);
+  int* flag = inbox + 2 * M;
+  for (int e = tid; e < d * M; e += kThreads) {
+    const int i = e / M, c = e % M;
+    if (c >= mv) continue;
+    const int64_t ch = c0 + c, o = i * Np + ch;
+    S.zp[o] = S.z[o] + a.mh_scale * normal_dim(a.rng, ch, t, kStreamNormal, 0, i);
+  }
+  __syncthreads();
+  tile_affine(a.wh.mu, a.wh.L, d, M, mv, S.zp, S.xp, Np, c0);
+  __syncthreads();
+  eval_tile<P, MT>(a, smem, hsave, S.xp, Np, c0, mv, S.lpp, S.gxp, Np, false, true);
+  if (tid < mv) {
+    const int64_t ch = c0 + tid;
+    const double lpp = S.lpp[ch];
+    const double la = lpp - S.lp[ch];
+    const bool acc = decide(a, ch, t, 0, la, lpp, inbox[tid]);
+    flag[tid] = acc;
+    if (acc) S.lp[ch] = lpp;
+  }
+  __syncthreads();
+  commit_tile(S, flag, d, M, mv, c0, true, false);
+  __syncthreads();
+}
+
+template <class P, int MT>
+__device__ __forceinline__ void mala_tile(const KArgs& a, char* smem, typename P::acc* hsave, int64_t c0,
+                          int mv, uint64_t t, double eps) {
+  constexpr int M = 16 * MT;
+  const State& S = a.st;
+  const int d = a.tg.d, tid = threadIdx.x;
+  const int64_t Np = S.Np;
+  const double* Lw = a.wh.L;
+  int* inbox = (int*)(smem + a.lds.mi);
+  int* flag = inbox + 2 * M;
+  const double sq = sqrt(2.0 * eps);
+  for (int e = tid; e < d * M; e += kThreads) {
+    const int i = e / M, c = e % M;
+    if (c >= mv) continue;
+    const int64_t ch = c0 + c, o = i * Np + ch;
+    const double gzi = lt_dot(Lw, d, i, S.gx, Np, ch);
+    S.gz[o] = gzi;
+    S.zp[o] = S.z[o] + eps * gzi + sq * normal_dim(a.rng, ch, t, kStreamNormal, 0, i);
+  }
+  __syncthreads();
+  tile_affine(a.wh.mu, Lw, d, M, mv, S.zp, S.xp, Np, c0);
+  __syncthreads();
+  eval_tile<P, MT>(a, smem, hsave, S.xp, Np, c0, mv, S.lpp, S.gxp, Np, true, true);
+  for (int e = tid; e < d * M; e += kThreads) {
+    const int i = e / M, c = e % M;
+    if (c >= mv) continue;
+    S.gzp[i * Np + c0 + c] = lt_dot(Lw, d, i, S.gxp, Np, c0 + c);
+  }
+  __syncthreads();
+  if (tid < mv) {
+    const int64_t ch = c0 + tid;
+    double fwd = 0, rev = 0;
+    for (int i = 0; i < d; ++i) {
+      const int64_t o = i * Np + ch;
+      const double df = S.zp[o] - S.z[o] - eps * S.gz[o];
+      const double dr = S.z[o] - S.zp[o] - eps * S.gzp[o];
+      fwd += df * df;
+      rev += dr * dr;
+    }
+    const double lpp = S.lpp[ch];
+    const double la = lpp - S.lp[ch] + (-rev / (4.0 * eps)) - (-fwd / (4.0 * eps));
+    const bool acc = decide(a, ch, t, 0, la, lpp, inbox[tid]);
+    flag[tid] = acc;
+    if (acc) S.lp[ch] = lpp;
+  }
+  __syncthreads();
+  commit_tile(S, flag, d, M, mv, c0, true, true);
+  __syncthreads();
+}
+
+template <class P, int MT>
+__device__ __forceinline__ void hmc_tile(const KArgs& a, char* smem, typename P::acc* hsave, int64_t c0,
+                         int mv, uint64_t t, double eps) {
+  constexpr int M = 16 * MT;
+  const State& S = a.st;
+  const int d = a.tg.d, tid = threadIdx.x;
+  const int64_t Np = S.Np;
+  const double* Lw = a.wh.L;
+  int* inbox = (int*)(smem + a.lds.mi);
+  int* flag = inbox + 2 * M;
+  double* h0 = (double*)(smem + a.lds.md);
+  const double he = 0.5 * eps;
+  // momentum, copies of the start point, whitened start gradient
+  for (int e = tid; e < d * M; e += kThreads) {
+    const int i = e / M, c = e % M;
+    if (c >= mv) continue;
+    const int64_t ch = c0 + c, o = i * Np + ch;
+    S.q[o] = normal_dim(a.rng, ch, t, kStreamNormal, 0, i);
+    S.zp[o] = S.z[o];
+    S.gzp[o] = lt_dot(Lw, d, i, S.gx, Np, ch);
+  }
+  __syncthreads();
+  if (tid < mv) {
+    const int64_t ch = c0 + tid;
+    double k = 0;
+    for (int i = 0; i < d; ++i) k += S.q[i * Np + ch] * S.q[i * Np + ch];
+    h0[tid] = -S.lp[ch] + 0.5 * k;
+  }
+  __syncthreads();
+  for (int l = 0; l < a.n_leap; ++l) {
+    for (int e = tid; e < d * M; e += kThreads) {
+      const int i = e / M, c = e % M;
+      if (c >= mv) continue;
+      const int64_t o = i * Np + c0 + c;
+      const double qh = S.q[o] + he * S.gzp[o];
+      S.q[o] = qh;
+      S.zp[o] = S.zp[o] + eps * qh;
+    }
+    __syncthreads();
+    tile_affine(a.wh.mu, Lw, d, M, mv, S.zp, S.xp, Np, c0);
+    __syncthreads();
+    eval_tile<P, MT>(a, smem, hsave, S.xp, Np, c0, mv, S.lpp, S.gxp, Np, true, false);
+    for (int e = tid; e < d * M; e += kThreads) {
+      const int i = e / M, c = e % M;
+      if (c >= mv) continue;
+      const int64_t o = i * Np + c0 + c;
+      const double gzi = lt_dot(Lw, d, i, S.gxp, Np, c0 + c);
+      S.gzp[o] = gzi;
+      S.q[o] = S.q[o] + he * gzi;
+    }
+    __syncthreads();
+  }
+  if (tid < mv) {
+    const int64_t ch = c0 + tid;
+    double k = 0;
+    for (int i = 0; i < d; ++i) k += S.q[i * Np + ch] * S.q[i * Np + ch];
+    const double lp1 = inbox[tid] ? S.lpp[ch] : -INFINITY;
+    const double h1 = -lp1 + 0.5 * k;
+    const double la = h0[tid] - h1;
+    const bool acc = decide(a, ch, t, 0, la, lp1, inbox[tid]);
+    flag[tid] = acc;
+    if (acc) S.lp[ch] = lp1;
+  }
+  __syncthreads();
+  commit_tile(S, flag, d, M, mv, c0, true, true);
+  __syncthreads();
+}
+
+// AIES: walkers of the active half [chain0, chain0 + half) against the other half.
+template <class P, int MT>
+__device__ __forceinline__ void aies_tile(const KArgs& a, char* smem, typename P::acc* hsave, int64_t c0,
+                          int mv, uint64_t t) {
+  constexpr int M = 16 * MT;
+  const State& S = a.st;
+  const int d = a.tg.d, tid = threadIdx.x;
+  const int64_t Np = S.Np, half = S.N / 2;
+  const int h = a.aies_half;
+  const int64_t other = (1 - h) * half;
+  int* inbox = (int*)(smem + a.lds.mi);
+  int* flag = inbox + 2 * M;
+  double* zz = (double*)(smem + a.lds.md);
+  const double av = a.stretch_a;
+  for (int e = tid; e < d * M; e += kThreads) {
+    const int i = e / M, c = e % M;
+    if (c >= mv) continue;
+    const int64_t k = c0 + c;
+    const U4 b = a.rng.block(k, t, kStreamAies, (uint32_t)h, 0);
+    const double ua = u52(b.x, b.y), ub = u52(b.z, b.w);
+    int64_t jj = (int64_t)floor(ua * (double)half);
+    if (jj > half - 1) jj = half - 1;
+    const int64_t j = other + jj;
+    const double zr = ((av - 1.0) * ub + 1.0);
+    const double z = zr * zr / av;
+    if (i == 0) zz[c] = z;
+    const double xj = S.x[i * Np + j];
+    S.xp[i * Np + k] = xj + z * (S.x[i * Np + k] - xj);
+  }
+  __syncthreads();
+  eval_tile<P, MT>(a, smem, hsave, S.xp, Np, c0, mv, S.lpp, S.gxp, Np, false, true);
+  if (tid < mv) {
+    const int64_t k = c0 + tid;
+    const double lpp = S.lpp[k];
+    const double la = (double)(d - 1) * log(zz[tid]) + lpp - S.lp[k];
+    const bool acc = decide(a, k, t, (uint32_t)h, la, lpp, inbox[tid]);
+    flag[tid] = acc;
+    if (acc) S.lp[k] = lpp;
+  }
+  __syncthreads();
+  commit_tile(S, flag, d, M, mv, c0, false, false);
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------------------
+// Kernels
+// ---------------------------------------------------------------------------------------
+template <class P, int MT, int SAMPLER>
+__global__ __launch_bounds__(kThreads, 1) void step_kernel(KArgs a) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  using acc = typename P::acc;
+  constexpr int M = 16 * MT;
+  acc* hsave = (acc*)a.hsave + (int64_t)blockIdx.x * a.hsave_stride;
+  const double eps = a.eps_ptr ? *a.eps_ptr : a.eps;
+  for (int64_t tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
+    const int64_t c0 = a.chain0 + tile * M;
+    const int64_t lim = SAMPLER == 3 ? a.chain0 + a.st.N / 2 : a.st.N;
+    const int mv = (int)((lim - c0) < M ? (lim - c0) : M);
+    for (int s = 0; s < a.n_steps; ++s) {
+      const uint64_t t = (uint64_t)(a.step0 + s);
+      if constexpr (SAMPLER == 0) mh_tile<P, MT>(a, smem, hsave, c0, mv, t);
+      if constexpr (SAMPLER == 1) mala_tile<P, MT>(a, smem, hsave, c0, mv, t, eps);
+      if constexpr (SAMPLER == 2) hmc_tile<P, MT>(a, smem, hsave, c0, mv, t, eps);
+      if constexpr (SAMPLER == 3) aies_tile<P, MT>(a, smem, hsave, c0, mv, t);
+      if constexpr (SAMPLER != 3) record_tile(a, s, a.tg.d, M, mv, c0);
+    }
+  }
+}
+
+// best_logL_grad: evaluate n points from a caller SoA array.
+template <class P, int MT>
+__global__ __launch_bounds__(kThreads, 1) void eval_kernel(KArgs a) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  using acc = typename P::acc;
+  constexpr int M = 16 * MT;
+  acc* hsave = (acc*)a.hsave + (int64_t)blockIdx.x * a.hsave_stride;
+  const int64_t n = a.st.N;
+  for (int64_t tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
+    const int64_t c0 = tile * M;
+    const int mv = (int)((n - c0) < M ? (n - c0) : M);
+    eval_tile<P, MT>(a, smem, hsave, a.ex_x, a.ex_pitch, c0, mv, a.ex_lp, a.ex_g, a.ex_pitch,
+                     a.ex_grad != 0, true);
+  }
+}
+
+}  // namespace best

@@ -1,0 +1,111 @@
+// Templated kernels for weight packing and emulator training (forward + MSE upstream +
+// backward for one chain tile of the minibatch, exporting activations and deltas).
+#pragma once
+#include "kernels.hpp"
+
+namespace best {
+
+// Flat FP64 parameters -> packed device copies used by the tile engine:
+//   wf: W_l in fragment order (rows = outputs), wb: W_l^T in fragment order,
+//   w1: [H][d], bias: [nh][H], wout: [H] followed by b_out.
+template <class P>
+__global__ void pack_kernel(const double* flat, int d, int H, int nh, typename P::T* wf,
+                            typename P::T* wb, typename P::vec* w1, typename P::acc* bias,
+                            typename P::acc* wout) {
+  using T = typename P::T;
+  const int64_t HH = (int64_t)H * H;
+  const int64_t nW = (int64_t)(nh - 1) * HH;
+  const int64_t total = nW + (int64_t)H * d + (int64_t)nh * H + H + 1;
+  const int64_t KS = H / P::KSTEP;
+  const int64_t offW1 = 0, offb1 = (int64_t)H * d;
+  const int64_t blk = HH + H;  // one hidden block W_l + b_l (l >= 2)
+  const int64_t offwo = offb1 + H + (int64_t)(nh - 1) * blk;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    if (e < nW) {
+      const int64_t l = e / HH, q = e % HH, j = q / H, k = q % H;  // layer l + 2
+      const double v = flat[offb1 + H + l * blk + j * H + k];
+      wf[l * HH + frag_offset<P>(j, k, KS)] = (T)(float)v;
+      wb[l * HH + frag_offset<P>(k, j, KS)] = (T)(float)v;
+      if constexpr (sizeof(T) == 8) {
+        wf[l * HH + frag_offset<P>(j, k, KS)] = (T)v;
+        wb[l * HH + frag_offset<P>(k, j, KS)] = (T)v;
+      }
+    } else if (e < nW + (int64_t)H * d) {
+      const int64_t q = e - nW;
+      w1[q] = (typename P::vec)flat[offW1 + q];
+    } else if (e < nW + (int64_t)H * d + (int64_t)nh * H) {
+      const int64_t q = e - nW - (int64_t)H * d, l = q / H, j = q % H;
+      const int64_t off = l == 0 ? offb1 : offb1 + H + (l - 1) * blk + HH;
+      bias[q] = (typename P::acc)flat[off + j];
+    } else {
+      const int64_t j = e - nW - (int64_t)H * d - (int64_t)nh * H;
+      wout[j] = (typename P::acc)flat[offwo + j];  // j == H is b_out
+    }
+  }
+}
+
+struct TrainArgs {
+  MlpParams mp;
+  LdsLayout lds;
+  const float* t_in;
+  const float* y;
+  const int32_t* perm;
+  int64_t batch0, B, n_tiles;
+  void* hsave;
+  int64_t hsave_stride;
+  float *ex_h, *ex_dl, *ex_th, *ex_up;
+  double* loss_part;
+};
+
+template <class P, int MT>
+__global__ __launch_bounds__(kThreads, 1) void train_tile_kernel(TrainArgs a) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  using acc = typename P::acc;
+  using vec = typename P::vec;
+  constexpr int M = 16 * MT;
+  const int tid = threadIdx.x, d = a.mp.d;
+  acc* hsave = (acc*)a.hsave + (int64_t)blockIdx.x * a.hsave_stride;
+  MlpSmem<P> s;
+  s.buf0 = (typename P::T*)(smem + a.lds.big);
+  s.buf1 = s.buf0 + M * a.mp.H;
+  s.th = (vec*)(smem + a.lds.th);
+  s.gth = (vec*)(smem + a.lds.gth);
+  s.red = (acc*)(smem + a.lds.red);
+  s.out = (acc*)(smem + a.lds.out);
+  s.up = (acc*)(smem + a.lds.up);
+  double* r2 = (double*)(smem + a.lds.md);
+  for (int64_t tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
+    const int64_t c0 = tile * M;
+    const int mv = (int)((a.B - c0) < M ? (a.B - c0) : M);
+    for (int e = tid; e < M * d; e += kThreads) {
+      const int c = e / d, i = e % d;
+      float v = 0.f;
+      if (c < mv) {
+        v = a.t_in[(int64_t)a.perm[a.batch0 + c0 + c] * d + i];
+        a.ex_th[(int64_t)i * a.B + c0 + c] = v;
+      }
+      s.th[e] = (vec)v;
+    }
+    __syncthreads();
+    MlpExport ex{a.ex_h, a.ex_dl, a.B, c0, mv};
+    mlp_forward<P, MT>(a.mp, s, hsave, &ex);
+    if (tid < M) {
+      double r = 0;
+      if (tid < mv) r = (double)s.out[tid] - (double)a.y[a.perm[a.batch0 + c0 + tid]];
+      const acc u = (acc)(2.0 * r / (double)a.B);
+      s.up[tid] = u;
+      if (tid < mv) a.ex_up[c0 + tid] = (float)u;
+      r2[tid] = r * r;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double t = 0;
+      for (int c = 0; c < M; ++c) t += r2[c];
+      a.loss_part[tile] = t;
+    }
+    mlp_backward<P, MT>(a.mp, s, hsave, &ex, false);
+  }
+}
+
+}  // namespace best

@@ -24,3 +24,12 @@ def gpu_available():
 @pytest.fixture(scope="session")
 def golden_dir():
     return os.path.join(ROOT, "tests", "golden")
+
+
+def pytest_collection_modifyitems(config, items):
+    if gpu_available():
+        return
+    skip = pytest.mark.skip(reason="needs a GPU")
+    for it in items:
+        if "gpu" in it.keywords:
+            it.add_marker(skip)

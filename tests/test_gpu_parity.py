@@ -1,0 +1,251 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the same seeded
+inputs and the same Philox streams.
+
+Tolerances (stated here, derived in the design doc):
+  FP64 GEMMs  logL abs 1e-9 * (1 + |logL|), grad rel 1e-8
+  FP32 GEMMs  logL abs 2e-5 * (1 + |logL|), grad abs 2e-4 * (1 + |g|)
+  FP16 / BF16 the emulator term (coef * MLP) within 2e-2 (bf16) / 4e-3 (fp16) absolute
+  lockstep    accept decisions equal except where |log alpha - log u| < band
+              (1e-6 for FP32, 1e-9 for FP64); accepted states within 1e-4 relative (FP32)
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_2606_04895_amd as B
+from oracle import samplers as OS, target as OT, philox as OP
+from workloads import make_problem, small_problem
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": (1e-9, 1e-8), "fp32": (2e-5, 2e-4), "fp16": (4e-3, None), "bf16": (2e-2, None)}
+
+
+def _points(prob, n, seed, spread=2.0):
+    rng = np.random.default_rng(seed)
+    sd = np.sqrt(np.diag(prob["closed_cov"])) if prob.get("closed_cov") is not None else \
+        0.25 * (prob["upper"] - prob["lower"])
+    x = prob["gauss_mean"] + rng.normal(size=(n, prob["d"])) * sd * spread \
+        if prob.get("closed_cov") is not None else \
+        prob["lower"] + rng.uniform(size=(n, prob["d"])) * (prob["upper"] - prob["lower"])
+    return x
+
+
+def _check_eval(prob, prec, n, seed=0, ctx=None):
+    ctx = ctx or B.best_init(prob, n_chains=16, precision=prec, seed=1)
+    x = _points(prob, n, seed)
+    lp, g = B.best_logL_grad(ctx, x.T.copy())
+    lo, go = OT.log_target(prob, x)
+    tl, tg = TOL[prec]
+    scale = 1.0 + np.abs(lo)
+    err_l = np.abs(lp - lo) / scale
+    assert np.all(np.isfinite(lp)) and np.all(np.isfinite(g))
+    assert err_l.max() < tl, (prec, err_l.max())
+    if tg is not None:
+        gscale = 1.0 + np.abs(go)
+        err_g = np.abs(g.T - go) / gscale
+        assert err_g.max() < tg, (prec, err_g.max())
+    return err_l.max()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16", "fp16"])
+@pytest.mark.parametrize("n", [1, 37, 333])
+def test_logL_grad_small_problem(prec, n):
+    prob = small_problem(d=5, width=64, n_hidden=3, twist=True)
+    _check_eval(prob, prec, n)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_logL_grad_single_hidden_layer(prec):
+    prob = small_problem(d=3, width=128, n_hidden=1)
+    _check_eval(prob, prec, 50)
+
+
+@pytest.mark.parametrize("name,prec", [("c1", "fp64"), ("c2", "fp32"), ("c2", "bf16"),
+                                       ("c3", "bf16"), ("c5", "bf16"), ("c5", "fp32")])
+def test_logL_grad_config_shapes(name, prec):
+    prob = make_problem(name)
+    _check_eval(prob, prec, 203, seed=3)
+
+
+def test_logL_grad_full_c2_batch_sampled():
+    """C2 at its full 4096 chains in the launch configuration of the benchmark; the oracle
+    checks a sample of 256 chains one by one."""
+    prob = make_problem("c2")
+    for prec in ("fp32", "bf16"):
+        ctx = B.best_init(prob, n_chains=4096, precision=prec, seed=2)
+        x = _points(prob, 4096, 11)
+        xt = torch.tensor(x.T.copy(), device="cuda")
+        lp, g = B.best_logL_grad(ctx, xt)
+        idx = np.random.default_rng(0).choice(4096, 256, replace=False)
+        lo, go = OT.log_target(prob, x[idx])
+        tl, tg = TOL[prec]
+        assert np.max(np.abs(lp.cpu().numpy()[idx] - lo) / (1 + np.abs(lo))) < tl
+
+
+def test_box_and_nonfinite_handling():
+    prob = small_problem(d=4, width=64, n_hidden=2)
+    ctx = B.best_init(prob, n_chains=16, precision="fp32", seed=1)
+    x = np.stack([prob["gauss_mean"], prob["upper"] + 1.0, prob["lower"]]).T.copy()
+    lp, g = B.best_logL_grad(ctx, x)
+    assert np.isfinite(lp[0]) and lp[1] == -np.inf and np.isfinite(lp[2])
+    assert np.all(np.isfinite(g))
+
+
+def test_emulator_fallback_and_plain_model():
+    prob = make_problem("c4")
+    for mode in (1, 2):
+        p = dict(prob, plain_mode=mode)
+        ctx = B.best_init(p, n_chains=16, precision="fp32", seed=1)
+        rng = np.random.default_rng(5)
+        inside = p["train_lo"] + rng.uniform(size=(20, 6)) * (p["train_hi"] - p["train_lo"])
+        outside = p["lower"] + rng.uniform(size=(20, 6)) * (p["upper"] - p["lower"])
+        x = np.concatenate([inside, outside])
+        lp, g = B.best_logL_grad(ctx, x.T.copy())
+        lo, go = OT.log_target(p, x)
+        np.testing.assert_allclose(lp, lo, rtol=1e-9, atol=2e-5)
+        np.testing.assert_allclose(g.T, go, rtol=1e-7, atol=2e-4 * (1 + np.abs(go).max()))
+
+
+# ---------------------------------------------------------------------------------------
+# Lockstep single-step parity
+# ---------------------------------------------------------------------------------------
+def _oracle_from_gpu(prob, ctx):
+    x, lp, g = B.best_get_state(ctx)
+    mu, L = B.best_get_whitening(ctx)
+    W = dict(mu=mu, L=L)
+    st = OS.init_state(prob, W, x.T)
+    return x.T, W, st
+
+
+def _lockstep(prob, prec, sampler, n, steps=3, band=1e-6, state_tol=1e-4, **kw):
+    ctx = B.best_init(prob, n_chains=n, precision=prec, seed=0xBE57, init="gaussian",
+                      init_point=prob["gauss_mean"], init_scale=0.05)
+    mu = prob["gauss_mean"]
+    L = np.linalg.cholesky(prob["closed_cov"])
+    B.best_set_whitening(ctx, mu, L)
+    seed = 0xBE57
+    mism = 0
+    for s in range(steps):
+        t = B.best_get_step_counter(ctx)
+        x0, W, st = _oracle_from_gpu(prob, ctx)
+        if sampler == "aies":
+            lp0, _ = OT.log_target(prob, x0)
+            new, info = OS.aies_step(prob, dict(x=x0, lp=lp0), t, seed, kw["stretch_a"])
+            x_or = new["x"]
+        else:
+            fn = dict(mh=OS.mh_step, mala=OS.mala_step, hmc=OS.hmc_step)[sampler]
+            args = dict(mh=(kw.get("mh_scale"),), mala=(kw.get("eps"),),
+                        hmc=(kw.get("eps"), kw.get("n_leapfrog")))[sampler]
+            new, info = fn(prob, W, st, t, seed, *args)
+            x_or = W["mu"][None, :] + new["z"] @ W["L"].T
+        B.best_step(ctx, sampler, 1, **kw)
+        x1, _, _ = B.best_get_state(ctx)
+        x1 = x1.T
+        acc_gpu = np.any(x1 != x0, axis=1)
+        acc_or = info["accepted"]
+        bad = acc_gpu != acc_or
+        if bad.any():
+            gap = np.abs(info["log_alpha"] - info["log_u"])[bad]
+            assert np.all(gap < band), (sampler, prec, gap)
+            mism += int(bad.sum())
+        ok = ~bad
+        scale = np.abs(x_or[ok]) + np.abs(x_or[ok] - x0[ok]) + 1e-12
+        rel = np.abs(x1[ok] - x_or[ok]) / scale
+        assert rel.max() < state_tol, (sampler, prec, rel.max())
+        assert 0 < acc_or.mean() <= 1.0
+    return mism
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("sampler,kw", [
+    ("mh", dict(mh_scale=2.4 / np.sqrt(5))),
+    ("mala", dict(eps=0.4)),
+    ("hmc", dict(eps=0.3, n_leapfrog=5)),
+    ("aies", dict(stretch_a=2.0)),
+])
+def test_lockstep_small(prec, sampler, kw):
+    if prec == "fp64" and sampler in ("mala", "hmc"):
+        pytest.skip("FP64 gradient samplers are switched off in the library: an earlier build "
+                    "of this path faulted on the GPU and the cause is not yet shown")
+    prob = small_problem(d=5, width=64, n_hidden=3, twist=True)
+    band, tol = (1e-9, 1e-10) if prec == "fp64" else (1e-6, 1e-4)
+    _lockstep(prob, prec, sampler, 262, steps=3, band=band, state_tol=tol, **kw)
+
+
+@pytest.mark.parametrize("sampler,kw", [("mala", dict(eps=0.5)),
+                                        ("hmc", dict(eps=0.3, n_leapfrog=10))])
+def test_lockstep_c2_fp32(sampler, kw):
+    prob = make_problem("c2")
+    _lockstep(prob, "fp32", sampler, 1000, steps=2, **kw)
+
+
+def test_lockstep_c1_fp64_mh():
+    prob = make_problem("c1")
+    _lockstep(prob, "fp64", "mh", 64, steps=5, band=1e-9, state_tol=1e-10,
+              mh_scale=2.4 / np.sqrt(6))
+
+
+# ---------------------------------------------------------------------------------------
+# Determinism and error paths
+# ---------------------------------------------------------------------------------------
+def test_bitwise_determinism_across_runs_and_tile_widths():
+    prob = small_problem(d=5, width=64, n_hidden=3)
+    outs = []
+    for cpb in (16, 32, 16):
+        ctx = B.best_init(prob, n_chains=200, precision="fp32", seed=9, chains_per_block=cpb)
+        B.best_step(ctx, "mala", 7, eps=0.3)
+        outs.append(B.best_get_state(ctx)[0])
+    assert np.array_equal(outs[0], outs[2])
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_resume_from_checkpoint_is_bitwise():
+    prob = small_problem(d=5, width=64, n_hidden=2)
+    a = B.best_init(prob, n_chains=64, precision="fp32", seed=4)
+    B.best_step(a, "hmc", 6, eps=0.2, n_leapfrog=4)
+    xa = B.best_get_state(a)[0]
+    b = B.best_init(prob, n_chains=64, precision="fp32", seed=4)
+    B.best_step(b, "hmc", 3, eps=0.2, n_leapfrog=4)
+    x_mid = B.best_get_state(b)[0]
+    c = B.best_init(prob, n_chains=64, precision="fp32", seed=4)
+    B.best_set_state(c, x_mid)
+    B.best_set_step_counter(c, 3)
+    B.best_step(c, "hmc", 3, eps=0.2, n_leapfrog=4)
+    assert np.array_equal(B.best_get_state(c)[0], xa)
+
+
+def test_fp64_gradient_samplers_are_refused():
+    prob = small_problem(d=4, width=64, n_hidden=2)
+    ctx = B.best_init(prob, n_chains=32, precision="fp64", seed=1)
+    for s in ("mala", "hmc"):
+        with pytest.raises(B.BestError) as e:
+            B.best_step(ctx, s, 1, eps=0.1, n_leapfrog=2)
+        assert e.value.code == 5
+
+
+def test_error_codes():
+    prob = small_problem(d=4, width=64, n_hidden=2)
+    ctx = B.best_init(prob, n_chains=33, precision="fp32", seed=1)
+    with pytest.raises(B.BestError) as e:
+        B.best_step(ctx, "aies", 1, stretch_a=2.0)
+    assert e.value.code == 5
+    with pytest.raises(B.BestError) as e:
+        B.best_step(ctx, "hmc", 1, eps=0.1, n_leapfrog=0)
+    assert e.value.code == 1
+    with pytest.raises(B.BestError) as e:
+        B.best_step(ctx, "mh", 1, mh_scale=-1)
+    assert e.value.code == 1
+    bad_L = np.eye(4)
+    bad_L[0, 1] = 1.0
+    with pytest.raises(B.BestError):
+        B.best_set_whitening(ctx, np.zeros(4), bad_L)
+
+
+def test_nonfinite_weights_are_rejected_and_counted():
+    prob = small_problem(d=4, width=64, n_hidden=2)
+    p = prob["mlp_params"].copy()
+    p[3] = np.nan
+    ctx = B.best_init(prob, n_chains=32, precision="fp32", seed=1)
+    with pytest.raises(B.BestError):
+        B.best_set_mlp(ctx, p, 0.5)
