@@ -115,6 +115,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--seed", type=int, default=0xBE570002)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run a plain device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the sampler's chains "
@@ -131,6 +133,14 @@ def main():
         sys.exit(1)
     prob = make_problem(args.config)
     d, H, nh = prob["d"], prob["width"], prob["n_hidden"]
+    if args.calib_copy_mib:
+        n = args.calib_copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"# calibration copy: {n * 4} bytes read, {n * 4} bytes written", file=sys.stderr)
+        del src, dst
     precs = args.precisions.split(",")
     samplers = args.samplers.split(",")
     results = {}

@@ -235,6 +235,17 @@ int best_train_grad(best_trainer *t, const float *t_in, const float *y, int64_t 
 int best_trainer_get_params(best_trainer *t, double *out); /* host [nparams] */
 const char *best_trainer_last_error(const best_trainer *t);
 
+/* Standardise n training targets: out[i] = (y[i] - mean) / std with the population std.
+ * y: device FP64 [n]; out: device FP32 [n]; mean_std: host [2] receives (mean, std).  The
+ * emulator then predicts log L = mean + std * MLP.  n >= 2; synchronises `stream`. */
+int best_standardise(const double *y, int64_t n, float *out, double *mean_std, void *stream);
+
+/* Importance weights of emulator samples under the plain likelihood:
+ * w_i = exp(lp_i - le_i) / sum_j exp(lp_j - le_j), evaluated with the maximum subtracted;
+ * kish (host) = (sum w)^2 / sum w^2.  lp, le, w: device FP64 [n]; synchronises `stream`. */
+int best_importance_weights(const double *logl_plain, const double *logl_emu, int64_t n,
+                            double *w, double *kish, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -17,7 +17,8 @@ from ._abi import (BEST_AIES, BEST_BF16, BEST_FP16, BEST_FP32, BEST_FP64, BEST_H
 __all__ = ["BestError", "Ctx", "best_init", "best_logL_grad", "best_step", "best_adapt",
            "best_get_state", "best_set_state", "best_get_whitening", "best_set_whitening",
            "best_set_step_size", "best_get_step_counter", "best_set_step_counter",
-           "best_set_mlp", "best_ess", "best_mlp_nparams", "Trainer", "EmulatorFn"]
+           "best_set_mlp", "best_ess", "best_mlp_nparams", "best_standardise",
+           "best_importance_weights", "Trainer", "EmulatorFn"]
 
 INITS = {"uniform": A.BEST_INIT_UNIFORM, "replicated": A.BEST_INIT_REPLICATED,
          "gaussian": A.BEST_INIT_GAUSSIAN}
@@ -276,6 +277,31 @@ def best_ess(ctx, record, n=None):
     out = np.empty(ctx.d)
     ctx.check(_lib().best_ess(ctx.h, _tensor_ptr(record, "float32"), T, _dptr(out)))
     return out
+
+
+def best_standardise(y, stream=None):
+    """y: CUDA float64 tensor [n] -> (float32 tensor of standardised values, mean, std)."""
+    import torch
+    out = torch.empty(y.shape[0], dtype=torch.float32, device=y.device)
+    ms = np.empty(2)
+    rc = _lib().best_standardise(_tensor_ptr(y, "float64"), int(y.shape[0]),
+                                 _tensor_ptr(out, "float32"), _dptr(ms), _stream(stream))
+    if rc != A.BEST_OK:
+        raise BestError(rc, "best_standardise failed")
+    return out, float(ms[0]), float(ms[1])
+
+
+def best_importance_weights(logl_plain, logl_emu, stream=None):
+    """CUDA float64 tensors [n] -> (normalised weights tensor, Kish ESS)."""
+    import torch
+    w = torch.empty_like(logl_plain)
+    kish = np.empty(1)
+    rc = _lib().best_importance_weights(_tensor_ptr(logl_plain, "float64"),
+                                        _tensor_ptr(logl_emu, "float64"), int(w.shape[0]),
+                                        _tensor_ptr(w, "float64"), _dptr(kish), _stream(stream))
+    if rc != A.BEST_OK:
+        raise BestError(rc, "best_importance_weights failed")
+    return w, float(kish[0])
 
 
 class Trainer:

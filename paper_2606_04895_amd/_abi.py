@@ -99,6 +99,9 @@ EXPORTS = {
     "best_train_grad": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, _dp, _dp]),
     "best_trainer_get_params": (C.c_int, [C.c_void_p, _dp]),
     "best_trainer_last_error": (C.c_char_p, [C.c_void_p]),
+    "best_standardise": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, _dp, C.c_void_p]),
+    "best_importance_weights": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, _dp,
+                                          C.c_void_p]),
 }
 
 _LIB = None

@@ -1067,3 +1067,34 @@ int best_trainer_get_params(best_trainer* t, double* out) {
 }
 
 }  // extern "C"
+
+extern "C" {
+
+int best_standardise(const double* y, int64_t n, float* out, double* mean_std, void* stream) {
+  if (!y || !out || !mean_std || n < 2) return BEST_EINVAL;
+  double* scratch = nullptr;
+  if (hipMalloc(&scratch, 520 * sizeof(double)) != hipSuccess) return BEST_ENOMEM;
+  double st[4];
+  hipError_t e = launch_standardise(y, n, out, scratch, st, (hipStream_t)stream);
+  (void)hipFree(scratch);
+  if (e != hipSuccess) return BEST_EHIP;
+  mean_std[0] = st[0] / (double)n;
+  mean_std[1] = std::sqrt(st[2] / (double)n);
+  return (std::isfinite(mean_std[1]) && mean_std[1] > 0) ? BEST_OK : BEST_EINVAL;
+}
+
+int best_importance_weights(const double* logl_plain, const double* logl_emu, int64_t n,
+                            double* w, double* kish, void* stream) {
+  if (!logl_plain || !logl_emu || !w || n < 1) return BEST_EINVAL;
+  double* scratch = nullptr;
+  if (hipMalloc(&scratch, 520 * sizeof(double)) != hipSuccess) return BEST_ENOMEM;
+  double st[4];
+  hipError_t e = launch_importance_weights(logl_plain, logl_emu, n, w, scratch, st,
+                                           (hipStream_t)stream);
+  (void)hipFree(scratch);
+  if (e != hipSuccess) return BEST_EHIP;
+  if (kish) kish[0] = st[2] * st[2] / st[3];
+  return std::isfinite(st[0]) ? BEST_OK : BEST_EINVAL;
+}
+
+}  // extern "C"

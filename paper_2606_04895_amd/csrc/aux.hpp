@@ -38,5 +38,9 @@ hipError_t launch_dw(const float* dl, const float* h, const float* th, const flo
                      int64_t B, int d, int H, int nh, double* grad, const int64_t* offs,
                      const int64_t* w_offs_host, hipStream_t s);
 hipError_t launch_sum(const double* part, int n, double scale, double* out, hipStream_t s);
+hipError_t launch_standardise(const double* y, int64_t n, float* out, double* scratch,
+                              double* stats_host, hipStream_t s);
+hipError_t launch_importance_weights(const double* lp, const double* le, int64_t n, double* w,
+                                     double* scratch, double* stats_host, hipStream_t s);
 
 }  // namespace best

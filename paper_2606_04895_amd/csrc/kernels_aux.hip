@@ -384,6 +384,66 @@ __global__ void sum_kernel(const double* part, int n, double scale, double* out)
   if (threadIdx.x == 0) *out = v * scale;
 }
 
+// ---- standardisation and importance weights (fixed-order two-stage reductions) ---------
+// mode 0: sum a;  1: sum (a - s)^2;  2: max (a - b);  3: sum e, sum e^2 with e = exp(a - b - s)
+__global__ void reduce_partial_kernel(int mode, const double* a, const double* b, int64_t n,
+                                      double s, double* part) {
+  __shared__ double sh[kThreads];
+  __shared__ double sh2[kThreads];
+  const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t i0 = blockIdx.x * per, i1 = min(n, i0 + per);
+  double v = mode == 2 ? -INFINITY : 0.0, v2 = 0.0;
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += kThreads) {
+    if (mode == 0) v += a[i];
+    else if (mode == 1) { const double r = a[i] - s; v += r * r; }
+    else if (mode == 2) v = fmax(v, a[i] - b[i]);
+    else { const double e = exp(a[i] - b[i] - s); v += e; v2 += e * e; }
+  }
+  sh[threadIdx.x] = v;
+  sh2[threadIdx.x] = v2;
+  __syncthreads();
+  for (int k = kThreads / 2; k > 0; k >>= 1) {
+    if (threadIdx.x < k) {
+      if (mode == 2) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + k]);
+      else sh[threadIdx.x] += sh[threadIdx.x + k];
+      sh2[threadIdx.x] += sh2[threadIdx.x + k];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = sh[0];
+    part[2 * blockIdx.x + 1] = sh2[0];
+  }
+}
+
+__global__ void reduce_final_kernel(int mode, const double* part, int nb, double* out) {
+  if (threadIdx.x != 0) return;
+  double v = mode == 2 ? -INFINITY : 0.0, v2 = 0.0;
+  for (int k = 0; k < nb; ++k) {
+    if (mode == 2) v = fmax(v, part[2 * k]);
+    else v += part[2 * k];
+    v2 += part[2 * k + 1];
+  }
+  out[0] = v;
+  out[1] = v2;
+}
+
+__global__ void standardise_kernel(const double* y, int64_t n, const double* stats, float* out) {
+  // stats = [sum, -, sum sq dev, -]: mean = sum / n, sigma = sqrt(sum sq dev / n)
+  const double mu = stats[0] / (double)n, sig = sqrt(stats[2] / (double)n);
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = (float)((y[i] - mu) / sig);
+}
+
+__global__ void weights_kernel(const double* a, const double* b, int64_t n, const double* st,
+                               double* w) {
+  // st = [max, -, sum e, sum e^2]
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    w[i] = exp(a[i] - b[i] - st[0]) / st[2];
+}
+
 }  // namespace best
 
 // ---------------------------------------------------------------------------------------
@@ -484,6 +544,52 @@ hipError_t launch_dw(const float* dl, const float* h, const float* th, const flo
 hipError_t launch_sum(const double* part, int n, double scale, double* out, hipStream_t s) {
   hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(kThreads), 0, s, part, n, scale, out);
   return hipGetLastError();
+}
+
+
+static hipError_t reduce2(int mode, const double* a, const double* b, int64_t n, double shift,
+                          double* part, double* out, hipStream_t s) {
+  const int nb = 256;
+  hipLaunchKernelGGL(reduce_partial_kernel, dim3(nb), dim3(kThreads), 0, s, mode, a, b, n,
+                     shift, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(64), 0, s, mode, part, nb, out);
+  return hipGetLastError();
+}
+
+// scratch: >= 512 + 4 doubles of device memory
+hipError_t launch_standardise(const double* y, int64_t n, float* out, double* scratch,
+                              double* stats_host, hipStream_t s) {
+  double* part = scratch;
+  double* st = scratch + 512;
+  hipError_t e = reduce2(0, y, nullptr, n, 0.0, part, st, s);
+  if (e != hipSuccess) return e;
+  double sum[2];
+  if ((e = hipMemcpyAsync(sum, st, 16, hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+  const double mu = sum[0] / (double)n;
+  if ((e = reduce2(1, y, nullptr, n, mu, part, st + 2, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(standardise_kernel, dim3(grid_for(n)), dim3(kThreads), 0, s, y, n, st, out);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = hipMemcpyAsync(stats_host, st, 32, hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+  return hipStreamSynchronize(s);
+}
+
+hipError_t launch_importance_weights(const double* lp, const double* le, int64_t n, double* w,
+                                     double* scratch, double* stats_host, hipStream_t s) {
+  double* part = scratch;
+  double* st = scratch + 512;
+  hipError_t e = reduce2(2, lp, le, n, 0.0, part, st, s);
+  if (e != hipSuccess) return e;
+  double mx[2];
+  if ((e = hipMemcpyAsync(mx, st, 16, hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+  if ((e = reduce2(3, lp, le, n, mx[0], part, st + 2, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(weights_kernel, dim3(grid_for(n)), dim3(kThreads), 0, s, lp, le, n, st, w);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = hipMemcpyAsync(stats_host, st, 32, hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+  return hipStreamSynchronize(s);
 }
 
 }  // namespace best

@@ -1,0 +1,218 @@
+"""GPU parity for adaptation (moments + jittered Cholesky), dual averaging, ESS, training
+(MSE gradient, Adam) and posterior recovery, against the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2606_04895_amd as B
+from oracle import adapt as OA, ess as OE, train as OTR, target as OT
+from workloads import (ar1_chains, latin_hypercube, make_problem, minibatch_permutations,
+                       small_problem, xavier_mlp)
+
+pytestmark = pytest.mark.gpu
+
+
+def _ctx_at_mean(prob, n, prec="fp32", seed=3):
+    ctx = B.best_init(prob, n_chains=n, precision=prec, seed=seed, init="gaussian",
+                      init_point=prob["gauss_mean"], init_scale=0.5)
+    B.best_set_whitening(ctx, prob["gauss_mean"], np.linalg.cholesky(prob["closed_cov"]))
+    return ctx
+
+
+def test_adapt_window_matches_oracle_moments_and_cholesky():
+    prob = small_problem(d=5, width=64, n_hidden=2)
+    n, T = 300, 40
+    ctx = _ctx_at_mean(prob, n)
+    rec = torch.empty((T, 5, n), dtype=torch.float32, device="cuda")
+    B.best_step(ctx, "mala", T, eps=0.3, record=rec)
+    info = B.best_adapt(ctx, samples=rec, update_mean=True)
+    mu, L = B.best_get_whitening(ctx)
+    samples = rec.double().cpu().numpy().transpose(0, 2, 1)  # (T, n, d)
+    m_ref, c_ref = OA.ensemble_moments(samples)
+    L_ref, jit = OA.regularised_cholesky(c_ref)
+    np.testing.assert_allclose(mu, m_ref, rtol=1e-10, atol=1e-10)
+    np.testing.assert_allclose(L, L_ref, rtol=1e-8, atol=1e-10)
+    assert info["jitter"] == 0.0
+    assert info["logdet"] == pytest.approx(np.sum(np.log(np.diag(L_ref))), rel=1e-10)
+    # every chain is re-whitened: a following MALA step still matches the state
+    x, lp, g = B.best_get_state(ctx)
+    lo, _ = OT.log_target(prob, x.T)
+    np.testing.assert_allclose(lp, lo, atol=2e-5 * (1 + np.abs(lo).max()))
+
+
+def test_adapt_rank_one_ensemble_takes_jitter_path():
+    prob = small_problem(d=4, width=64, n_hidden=2)
+    n = 64
+    ctx = _ctx_at_mean(prob, n)
+    t = np.linspace(-1, 1, n)
+    v = np.array([1.0, 0.5, -0.25, 0.1])
+    x = prob["gauss_mean"][:, None] + v[:, None] * t[None, :]
+    B.best_set_state(ctx, x)
+    info = B.best_adapt(ctx, update_mean=True)
+    _, L = B.best_get_whitening(ctx)
+    m_ref, c_ref = OA.ensemble_moments(x.T)
+    L_ref, jit = OA.regularised_cholesky(c_ref)
+    assert info["jitter"] > 0 and info["jitter"] == pytest.approx(jit, rel=1e-12)
+    np.testing.assert_allclose(L, L_ref, rtol=1e-6, atol=1e-9)
+
+
+def test_adapt_collapsed_ensemble_reports_not_pd_and_keeps_whitening():
+    prob = small_problem(d=3, width=64, n_hidden=2)
+    ctx = _ctx_at_mean(prob, 32)
+    mu0, L0 = B.best_get_whitening(ctx)
+    B.best_set_state(ctx, np.tile(prob["gauss_mean"][:, None], (1, 32)))
+    with pytest.raises(B.BestError) as e:
+        B.best_adapt(ctx, update_mean=True)
+    assert e.value.code == 4
+    mu1, L1 = B.best_get_whitening(ctx)
+    assert np.array_equal(L0, L1) and np.array_equal(mu0, mu1)
+
+
+@pytest.mark.parametrize("sampler,target", [("mala", 0.57), ("hmc", 0.8)])
+def test_dual_averaging_reaches_target_acceptance(sampler, target):
+    prob = make_problem("c2")
+    ctx = _ctx_at_mean(prob, 2048)
+    B.best_set_step_size(ctx, 0.05)
+    B.best_step(ctx, sampler, 300, adapt_eps=True, target_accept=target, n_leapfrog=10)
+    B.best_adapt(ctx, update_mean=False, finalize_da=True)
+    st = B.best_step(ctx, sampler, 150, n_leapfrog=10)
+    acc = st["accepted"] / (150 * 2048)
+    assert abs(acc - target) < 0.06, (sampler, acc, st["eps"])
+
+
+def test_ess_matches_oracle_on_ar1_chains():
+    prob = small_problem(d=3, width=64, n_hidden=2)
+    n, T = 256, 600
+    ctx = _ctx_at_mean(prob, n)
+    rng = np.random.default_rng(7)
+    data = np.stack([ar1_chains(rng, r, n, T) for r in (0.2, 0.6, 0.9)])  # (d, n, T)
+    rec = torch.tensor(data.transpose(2, 0, 1).copy(), dtype=torch.float32, device="cuda")
+    ess_gpu = B.best_ess(ctx, rec)
+    r32 = rec.double().cpu().numpy()  # the same float32 values
+    ess_ref = np.array([OE.ess(r32[:, i, :].T) for i in range(3)])
+    np.testing.assert_allclose(ess_gpu, ess_ref, rtol=1e-6)
+
+
+def test_ess_long_lag_extension():
+    """Strongly correlated chains need lags beyond the first 128-lag pass."""
+    prob = small_problem(d=3, width=64, n_hidden=2)
+    n, T = 64, 3000
+    ctx = _ctx_at_mean(prob, n)
+    rng = np.random.default_rng(8)
+    data = np.stack([ar1_chains(rng, r, n, T) for r in (0.99, 0.98, 0.5)])
+    rec = torch.tensor(data.transpose(2, 0, 1).copy(), dtype=torch.float32, device="cuda")
+    ess_gpu = B.best_ess(ctx, rec)
+    r32 = rec.double().cpu().numpy()
+    ess_ref = np.array([OE.ess(r32[:, i, :].T) for i in range(3)])
+    np.testing.assert_allclose(ess_gpu, ess_ref, rtol=1e-6)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_training_gradient_matches_oracle(prec):
+    d, w, nh, B_ = 6, 128, 3, 96
+    rng = np.random.default_rng(9)
+    p = xavier_mlp(rng, d, w, nh)
+    p += rng.normal(0, 0.02, size=p.size)
+    th = rng.uniform(-1, 1, size=(B_, d))
+    y = rng.normal(size=B_)
+    tr = B.Trainer(d, w, nh, p, precision=prec)
+    loss, g = tr.grad(torch.tensor(th, dtype=torch.float32, device="cuda"),
+                      torch.tensor(y, dtype=torch.float32, device="cuda"))
+    th32 = th.astype(np.float32).astype(np.float64)
+    y32 = y.astype(np.float32).astype(np.float64)
+    loss_ref, g_ref = OTR.mse_loss_grad(p, th32, y32, d, w, nh)
+    tol = 2e-4 if prec == "fp32" else 3e-2
+    assert abs(loss - loss_ref) < tol * (1 + loss_ref)
+    assert np.max(np.abs(g - g_ref)) < tol * (np.abs(g_ref).max() + 1e-3)
+
+
+def test_first_adam_step_matches_oracle():
+    d, w, nh, B_ = 6, 64, 2, 64
+    rng = np.random.default_rng(10)
+    p = xavier_mlp(rng, d, w, nh)
+    th = rng.uniform(-1, 1, size=(B_, d))
+    y = rng.normal(size=B_)
+    tr = B.Trainer(d, w, nh, p, precision="fp32")
+    perm = torch.arange(B_, dtype=torch.int32, device="cuda")
+    tht = torch.tensor(th, dtype=torch.float32, device="cuda")
+    yt = torch.tensor(y, dtype=torch.float32, device="cuda")
+    _, g_gpu = tr.grad(tht, yt)
+    tr.epoch(tht, yt, perm, B_, 1e-3, 1e-3, 0, 1)
+    p1 = tr.params()
+    ref = OTR.Adam(p.size).step(p, g_gpu, 1e-3)
+    np.testing.assert_allclose(p1, ref, rtol=0, atol=1e-12)
+
+
+def test_training_reduces_loss_on_plain_model_pairs():
+    prob = make_problem("c4")
+    n = 4096
+    rng = np.random.default_rng(11)
+    u = latin_hypercube(rng, n, 6)
+    x = prob["train_lo"] + u * (prob["train_hi"] - prob["train_lo"])
+    ctx = B.best_init(prob, n_chains=16, precision="fp32", seed=1)
+    ll, _ = B.best_logL_grad(ctx, x.T.copy(), want_grad=False)
+    yh, mu, sig = OTR.standardise(ll)
+    th = (x - prob["in_center"]) * prob["in_invscale"]
+    tr = B.Trainer(6, 128, 3, xavier_mlp(rng, 6, 128, 3), precision="fp32")
+    tht = torch.tensor(th, dtype=torch.float32, device="cuda")
+    yt = torch.tensor(yh, dtype=torch.float32, device="cuda")
+    perms = minibatch_permutations(rng, n, 30)
+    losses = []
+    for e in range(30):
+        pe = torch.tensor(perms[e], device="cuda")
+        losses.append(tr.epoch(tht, yt, pe, 256, 3e-3, 1e-4, e * 16, 30 * 16))
+    assert losses[-1] < 0.05 * losses[0], losses
+
+
+@pytest.mark.parametrize("sampler,kw", [("mala", dict(eps=0.8)), ("hmc", dict(eps=0.5, n_leapfrog=5)),
+                                        ("mh", dict(mh_scale=2.4 / np.sqrt(6))),
+                                        ("aies", dict(stretch_a=2.0))])
+def test_gaussian_posterior_recovery(sampler, kw):
+    prob = make_problem("c2", with_mlp=False)
+    n = 4096
+    ctx = _ctx_at_mean(prob, n)
+    steps = 300 if sampler != "aies" else 600
+    B.best_step(ctx, sampler, 100, **kw)
+    rec = torch.empty((steps, 6, n), dtype=torch.float32, device="cuda")
+    B.best_step(ctx, sampler, steps, record=rec, **kw)
+    s = rec.double().cpu().numpy().transpose(0, 2, 1)
+    m, c = OA.ensemble_moments(s)
+    ess = B.best_ess(ctx, rec)
+    sd = np.sqrt(np.diag(prob["closed_cov"]))
+    z = np.abs(m - prob["closed_mean"]) / (sd / np.sqrt(ess))
+    assert np.all(z < 5), (sampler, z)
+    Li = np.linalg.inv(np.linalg.cholesky(prob["closed_cov"]))
+    dev = np.linalg.norm(Li @ c @ Li.T - np.eye(6), 2)
+    assert dev < 0.05 + 5 * np.sqrt(2.0 / ess.min()), (sampler, dev, ess.min())
+
+
+def test_standardise_and_importance_weights_match_oracle():
+    rng = np.random.default_rng(12)
+    y = rng.normal(size=5000) * 40 - 1200
+    out, mu, sig = B.best_standardise(torch.tensor(y, device="cuda"))
+    yh, mu_r, sig_r = OTR.standardise(y)
+    assert mu == pytest.approx(mu_r, rel=1e-13) and sig == pytest.approx(sig_r, rel=1e-12)
+    np.testing.assert_allclose(out.cpu().numpy(), yh.astype(np.float32), rtol=1e-6, atol=1e-6)
+    lp = rng.normal(size=5000) * 3 - 1000
+    le = lp + rng.normal(size=5000) * 0.3
+    w, kish = B.best_importance_weights(torch.tensor(lp, device="cuda"),
+                                        torch.tensor(le, device="cuda"))
+    w_r = OTR.importance_weights(lp, le)
+    np.testing.assert_allclose(w.cpu().numpy(), w_r, rtol=1e-12)
+    assert kish == pytest.approx(OTR.kish_ess(w_r), rel=1e-12)
+    w, kish = B.best_importance_weights(torch.tensor(lp, device="cuda"),
+                                        torch.tensor(lp, device="cuda"))
+    assert kish == pytest.approx(5000, rel=1e-12)
+
+
+def test_autograd_wrapper_returns_the_hand_written_gradient():
+    prob = make_problem("c2")
+    ctx = B.best_init(prob, n_chains=64, precision="fp32", seed=1)
+    rng = np.random.default_rng(13)
+    x = prob["gauss_mean"] + rng.normal(size=(20, 6)) * np.sqrt(np.diag(prob["closed_cov"]))
+    xt = torch.tensor(x.T.copy(), device="cuda", requires_grad=True)
+    lp = B.EmulatorFn.apply(ctx, xt)
+    (lp * torch.arange(1, 21, device="cuda", dtype=torch.float64)).sum().backward()
+    _, go = OT.log_target(prob, x)
+    ref = go * np.arange(1, 21)[:, None]
+    np.testing.assert_allclose(xt.grad.cpu().numpy().T, ref, rtol=2e-4, atol=2e-4)

@@ -160,8 +160,8 @@ def _lockstep(prob, prec, sampler, n, steps=3, band=1e-6, state_tol=1e-4, **kw):
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("sampler,kw", [
     ("mh", dict(mh_scale=2.4 / np.sqrt(5))),
-    ("mala", dict(eps=0.4)),
-    ("hmc", dict(eps=0.3, n_leapfrog=5)),
+    ("mala", dict(eps=0.008)),
+    ("hmc", dict(eps=0.07, n_leapfrog=5)),
     ("aies", dict(stretch_a=2.0)),
 ])
 def test_lockstep_small(prec, sampler, kw):
