@@ -197,8 +197,12 @@ int best_step(best_ctx *h, int32_t sampler, int64_t n_steps, const best_step_par
 int best_adapt(best_ctx *h, const best_adapt_params *p, best_adapt_info *out);
 
 /* ---- state, whitening, diagnostics ---- */
+/* Checkpoint / resume.  get: x [d][n], logL [n], grad [d][n] (any may be NULL).  set: x,
+ * and either both logL and grad (restored as given, so a resumed run continues bit-for-bit
+ * with the same step counter) or neither (re-evaluated). */
 int best_get_state(best_ctx *h, double *x, double *logL, double *grad, uint32_t flags);
-int best_set_state(best_ctx *h, const double *x, uint32_t flags); /* re-evaluates */
+int best_set_state(best_ctx *h, const double *x, const double *logL, const double *grad,
+                   uint32_t flags);
 int best_get_whitening(best_ctx *h, double *mu, double *L);       /* host, [d], [d*d] */
 int best_set_whitening(best_ctx *h, const double *mu, const double *L);
 uint64_t best_get_step_counter(const best_ctx *h);

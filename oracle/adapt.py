@@ -8,9 +8,9 @@ Readings used here (the paper gives no formulas for these):
   * moments are pooled over every chain and every retained step of the window; the
     covariance uses the unbiased 1/(n-1) normalisation; the whitening mean is the
     ensemble mean;
-  * regularisation: symmetrise, try Cholesky; on failure add lam * mean(diag S) * I with
-    lam = 1e-10, 1e-9, ..., 1e-2 and retry; if all fail the factorisation is reported as
-    failed;
+  * regularisation: symmetrise, try Cholesky (a pivot must exceed 1e-12 * mean(diag S) to
+    count as positive); on failure add lam * mean(diag S) * I with lam = 1e-10, 1e-9, ...,
+    1e-2 and retry; if all fail the factorisation is reported as failed;
   * step size: dual averaging of Hoffman & Gelman (2014, Sec. 3.2) on the chain-averaged
     acceptance probability, gamma = 0.05, t0 = 10, kappa = 0.75, mu = log(10 eps0).
 """
@@ -29,8 +29,12 @@ def ensemble_moments(samples):
     return mean, cov
 
 
-def cholesky_lower(a):
-    """Plain Cholesky-Banachiewicz, returns L or None if a pivot is not positive/finite."""
+PIVOT_FLOOR = 1e-12
+
+
+def cholesky_lower(a, floor=0.0):
+    """Plain Cholesky-Banachiewicz; returns L, or None if a pivot is not finite and above
+    `floor` (numerical positive definiteness)."""
     a = np.asarray(a, dtype=np.float64)
     d = a.shape[0]
     L = np.zeros_like(a)
@@ -38,7 +42,7 @@ def cholesky_lower(a):
         for j in range(i + 1):
             s = a[i, j] - np.dot(L[i, :j], L[j, :j])
             if i == j:
-                if not (s > 0.0) or not np.isfinite(s):
+                if not (s > floor) or not np.isfinite(s):
                     return None
                 L[i, i] = np.sqrt(s)
             else:
@@ -47,15 +51,18 @@ def cholesky_lower(a):
 
 
 def regularised_cholesky(cov):
-    """Returns (L, jitter_used).  Raises np.linalg.LinAlgError if every jitter fails."""
+    """Returns (L, jitter_used).  Raises np.linalg.LinAlgError if every jitter fails.
+    A pivot counts as positive only above PIVOT_FLOOR * mean(diag S), so a rank-deficient
+    covariance takes the jitter path whatever its rounding."""
     s = 0.5 * (np.asarray(cov) + np.asarray(cov).T)
-    L = cholesky_lower(s)
+    scale = float(np.mean(np.diag(s)))
+    floor = PIVOT_FLOOR * scale if np.isfinite(scale) else 0.0
+    L = cholesky_lower(s, floor)
     if L is not None:
         return L, 0.0
-    scale = float(np.mean(np.diag(s)))
     lam = 1e-10
     while lam <= 1e-2 * (1 + 1e-12):
-        L = cholesky_lower(s + lam * scale * np.eye(s.shape[0]))
+        L = cholesky_lower(s + lam * scale * np.eye(s.shape[0]), floor)
         if L is not None:
             return L, lam * scale
         lam *= 10.0

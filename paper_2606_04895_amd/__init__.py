@@ -236,10 +236,15 @@ def best_get_state(ctx):
     return x, lp, g
 
 
-def best_set_state(ctx, x):
+def best_set_state(ctx, x, logL=None, grad=None):
+    """Host arrays x [d][n] and optionally logL [n] and grad [d][n] (both or neither)."""
     xa = _f64(x)
     assert xa.shape == (ctx.d, ctx.n_chains)
-    ctx.check(_lib().best_set_state(ctx.h, xa.ctypes.data_as(C.c_void_p), A.BEST_HOST_PTRS))
+    la, ga = _f64(logL), _f64(grad)
+    ctx.check(_lib().best_set_state(ctx.h, xa.ctypes.data_as(C.c_void_p),
+                                    la.ctypes.data_as(C.c_void_p) if la is not None else None,
+                                    ga.ctypes.data_as(C.c_void_p) if ga is not None else None,
+                                    A.BEST_HOST_PTRS))
 
 
 def best_get_whitening(ctx):

@@ -82,7 +82,7 @@ EXPORTS = {
                             C.POINTER(StepStats)]),
     "best_adapt": (C.c_int, [C.c_void_p, C.POINTER(AdaptParams), C.POINTER(AdaptInfo)]),
     "best_get_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32]),
-    "best_set_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32]),
+    "best_set_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32]),
     "best_get_whitening": (C.c_int, [C.c_void_p, _dp, _dp]),
     "best_set_whitening": (C.c_int, [C.c_void_p, _dp, _dp]),
     "best_get_step_counter": (C.c_uint64, [C.c_void_p]),

@@ -101,9 +101,15 @@ int tsize(int prec) { return prec == BEST_FP64 ? 8 : prec == BEST_FP32 ? 4 : 2; 
 int vasize(int prec) { return prec == BEST_FP64 ? 8 : 4; }
 int mt_max(int prec) { return prec == BEST_FP64 ? 2 : 4; }
 
-LdsLayout layout_for(int prec, int MT, int H, int d) {
-  return lds_layout(16 * MT, H, d, tsize(prec), vasize(prec), vasize(prec));
+LdsLayout layout_for(int prec, int MT, int H, int d, int nh, int lds_h) {
+  return lds_layout(16 * MT, H, d, nh, lds_h, tsize(prec), vasize(prec), vasize(prec));
 }
+
+// Packed hidden weights (forward and transposed copies) in the GEMM type.
+int64_t weight_bytes(int prec, int H, int nh) {
+  return 2LL * (nh - 1) * H * H * tsize(prec);
+}
+constexpr int64_t kL2Budget = 3LL << 20;  // of the 4 MiB L2 per XCD, leave room for state
 
 int64_t mlp_nparams_impl(int64_t d, int64_t w, int64_t nh) {
   return w * d + w + (nh - 1) * (w * w + w) + w + 1;
@@ -115,7 +121,7 @@ struct best_ctx {
   std::string err;
   hipStream_t stream = nullptr;
   int n_cu = 256;
-  int d = 0, H = 0, nh = 0, prec = 0, MT = 1;
+  int d = 0, H = 0, nh = 0, prec = 0, MT = 1, lds_h = 0;
   int64_t N = 0, Np = 0;
   uint64_t seed = 0, step = 0;
   Arena mem;
@@ -286,25 +292,30 @@ static int validate_problem(best_ctx* h, const best_problem* p, const best_confi
   return BEST_OK;
 }
 
+// Chain-tile width and activation storage.  Every tile streams all packed weights once per
+// evaluation.  If they fit in L2 the streaming is L2->CU bound, so all CUs should get a tile
+// (tiles >= CUs); otherwise the traffic beyond L2 scales with the number of tiles and the
+// widest tile that fits LDS is preferred.  Activations stay in LDS when there is room.
 static int choose_mt(best_ctx* h, const best_config* c) {
+  auto fits = [&](int mt, int lh) {
+    return layout_for(h->prec, mt, h->H, h->d, h->nh, lh).total <= kLdsMax;
+  };
+  int mt = 0;
   if (c->chains_per_block) {
-    h->MT = c->chains_per_block / 16;
-    if (layout_for(h->prec, h->MT, h->H, h->d).total > kLdsMax)
-      return fail(h, BEST_EINVAL, "chains_per_block needs more LDS than 160 KiB");
-    return BEST_OK;
-  }
-  int best_mt = 0;
-  for (int mt = mt_max(h->prec); mt >= 1; mt /= 2) {
-    if (layout_for(h->prec, mt, h->H, h->d).total > kLdsMax) continue;
-    if (best_mt == 0) best_mt = mt;  // largest that fits, as a fallback
-    if ((h->N + 16 * mt - 1) / (16 * mt) >= h->n_cu) {
-      best_mt = mt;
-      break;
+    mt = c->chains_per_block / 16;
+    if (!fits(mt, 0)) return fail(h, BEST_EINVAL, "chains_per_block needs more LDS than 160 KiB");
+  } else {
+    const bool l2_resident = weight_bytes(h->prec, h->H, h->nh) <= kL2Budget;
+    for (int m = mt_max(h->prec); m >= 1; m /= 2) {
+      if (!fits(m, 0)) continue;
+      mt = m;
+      if (!l2_resident) break;
+      if ((h->N + 16 * m - 1) / (16 * m) >= h->n_cu) break;
     }
-    best_mt = mt;  // keep shrinking towards more tiles
+    if (!mt) return fail(h, BEST_EINVAL, "MLP width too large for the LDS budget");
   }
-  if (!best_mt) return fail(h, BEST_EINVAL, "MLP width too large for the LDS budget");
-  h->MT = best_mt;
+  h->MT = mt;
+  h->lds_h = fits(mt, 1) ? 1 : 0;
   return BEST_OK;
 }
 
@@ -368,6 +379,7 @@ static int alloc_mlp(best_ctx* h) {
   h->mp.d = d;
   h->mp.H = H;
   h->mp.nh = nh;
+  h->mp.lds_h = h->lds_h;
   h->mp.wf = h->wf;
   h->mp.wb = h->wb;
   h->mp.w1 = h->w1;
@@ -417,7 +429,7 @@ int best_init(best_ctx** out, const best_problem* p, const best_config* c) {
   h->Np = (h->N + 63) / 64 * 64;
   h->seed = c->seed;
   if ((rc = choose_mt(h, c))) return bail(rc);
-  h->lds = layout_for(h->prec, h->MT, h->H, h->d);
+  h->lds = layout_for(h->prec, h->MT, h->H, h->d, h->nh, h->lds_h);
   if ((rc = upload_problem(h, p))) return bail(rc);
   if ((rc = alloc_mlp(h))) return bail(rc);
   if (p->plain_mode != 2) {
@@ -673,15 +685,27 @@ int best_get_state(best_ctx* h, double* x, double* logL, double* grad, uint32_t 
   return BEST_OK;
 }
 
-int best_set_state(best_ctx* h, const double* x, uint32_t flags) {
+int best_set_state(best_ctx* h, const double* x, const double* logL, const double* grad,
+                   uint32_t flags) {
   if (!h) return BEST_EINVAL;
   if (!x) return fail(h, BEST_EINVAL, "x is NULL");
   if (flags & ~BEST_HOST_PTRS) return fail(h, BEST_EINVAL, "unknown flags");
+  if ((logL == nullptr) != (grad == nullptr))
+    return fail(h, BEST_EINVAL, "pass both logL and grad, or neither");
   const hipMemcpyKind k = (flags & BEST_HOST_PTRS) ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
-  for (int i = 0; i < h->d; ++i)
+  for (int i = 0; i < h->d; ++i) {
     HIPCHK(h, hipMemcpyAsync(h->st.x + i * h->Np, x + i * h->N, h->N * 8, k, h->stream));
+    if (grad)
+      HIPCHK(h, hipMemcpyAsync(h->st.gx + i * h->Np, grad + i * h->N, h->N * 8, k, h->stream));
+  }
   int rc;
-  if ((rc = refresh_state(h)) || (rc = rewhiten(h))) return rc;
+  if (logL) {
+    HIPCHK(h, hipMemcpyAsync(h->st.lp, logL, h->N * 8, k, h->stream));
+    h->gx_stale = false;
+  } else if ((rc = refresh_state(h))) {
+    return rc;
+  }
+  if ((rc = rewhiten(h))) return rc;
   HIPCHK(h, hipStreamSynchronize(h->stream));
   return BEST_OK;
 }
@@ -954,8 +978,9 @@ int best_trainer_create(best_trainer** out, int32_t d, int32_t width, int32_t n_
   if (he != hipSuccess)
     return bail(tfail(t, BEST_EHIP, std::string("no usable HIP device: ") + hipGetErrorString(he)));
   t->MT = 2;
-  while (t->MT > 1 && layout_for(precision, t->MT, width, d).total > kLdsMax) t->MT /= 2;
-  t->lds = layout_for(precision, t->MT, width, d);
+  while (t->MT > 1 && layout_for(precision, t->MT, width, d, n_hidden, 0).total > kLdsMax) t->MT /= 2;
+  const int lds_h = layout_for(precision, t->MT, width, d, n_hidden, 1).total <= kLdsMax ? 1 : 0;
+  t->lds = layout_for(precision, t->MT, width, d, n_hidden, lds_h);
   if (t->lds.total > kLdsMax) return bail(tfail(t, BEST_EINVAL, "width too large for LDS"));
   if (!finite_all(init_params, t->np)) return bail(tfail(t, BEST_EINVAL, "init params must be finite"));
   const int ts = tsize(precision);
@@ -974,7 +999,7 @@ int best_trainer_create(best_trainer** out, int32_t d, int32_t width, int32_t n_
   if (hipMemsetAsync(t->m, 0, t->np * 8, t->stream) != hipSuccess ||
       hipMemsetAsync(t->v, 0, t->np * 8, t->stream) != hipSuccess)
     return bail(tfail(t, BEST_EHIP, "memset"));
-  t->mp = MlpParams{d, width, n_hidden, t->wf, t->wb, t->w1, t->bias, t->wout};
+  t->mp = MlpParams{d, width, n_hidden, lds_h, t->wf, t->wb, t->w1, t->bias, t->wout};
   t->grid_cap = t->n_cu * std::max(1, std::min(2, kLdsMax / t->lds.total));
   t->hsave_stride = (int64_t)n_hidden * width * 16 * t->MT;
   if (t->mem.alloc((char**)&t->hsave, (size_t)t->grid_cap * t->hsave_stride * 4) != hipSuccess)

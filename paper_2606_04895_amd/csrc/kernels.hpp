@@ -44,12 +44,12 @@ struct LdsLayout {
 
 __host__ __device__ inline int align16(int v) { return (v + 15) & ~15; }
 
-// Union region: {2 activation buffers} during the MLP, {R, PR, plain results, plain
-// scratch} during the FP64 assembly.
-__host__ __device__ inline LdsLayout lds_layout(int M, int H, int d, int tsize, int vsize,
-                                               int asize) {
+// Union region: {activation slots or ping-pong buffers + delta buffers} during the MLP,
+// {R, PR, plain results, plain scratch} during the FP64 assembly.
+__host__ __device__ inline LdsLayout lds_layout(int M, int H, int d, int nh, int lds_h,
+                                               int tsize, int vsize, int asize) {
   LdsLayout L;
-  const int mlp_bytes = 2 * M * H * tsize;
+  const int mlp_bytes = (lds_h ? nh + 2 : 2) * M * H * tsize;
   const int asm_bytes = 8 * (2 * d * M + M + M * d + kMaxD + 3 * kMaxTerms + kWaves * 32);
   L.big = 0;
   int o = align16(mlp_bytes > asm_bytes ? mlp_bytes : asm_bytes);
@@ -217,9 +217,7 @@ __device__ __forceinline__ void eval_tile(const KArgs& a, char* smem, typename P
   const Target& tg = a.tg;
   const int tid = threadIdx.x, d = tg.d;
   const LdsLayout& L = a.lds;
-  MlpSmem<P> s;
-  s.buf0 = (typename P::T*)(smem + L.big);
-  s.buf1 = s.buf0 + M * a.mp.H;
+  MlpSmem<P> s = mlp_smem<P, MT>(smem + L.big, a.mp);
   s.th = (vec*)(smem + L.th);
   s.gth = (vec*)(smem + L.gth);
   s.red = (acc*)(smem + L.red);
@@ -248,8 +246,8 @@ __device__ __forceinline__ void eval_tile(const KArgs& a, char* smem, typename P
   __syncthreads();
 
   if (tg.plain_mode != 2) {
-    mlp_forward<P, MT>(a.mp, s, hsave, nullptr);
-    if (grad) mlp_backward<P, MT>(a.mp, s, hsave, nullptr, true);
+    mlp_forward<P, MT>(a.mp, s, hsave, nullptr, grad);
+    if (grad) mlp_backward<P, MT>(a.mp, s, hsave, nullptr, true, true);
   }
 
   // FP64 assembly region (reuses the activation buffers)
@@ -334,6 +332,25 @@ __device__ __forceinline__ void tile_affine(const double* __restrict__ mu, const
   }
 }
 
+// z = L^{-1}(x - mu) for the tile's chains (forward substitution, one thread per chain).
+// Every MH / MALA / HMC step starts from the whitened coordinates of the stored x, so a
+// chain's state is exactly (x, log pi, grad log pi) and a restored state continues
+// bit-for-bit.
+__device__ __forceinline__ void tile_whiten(const double* __restrict__ mu,
+                                            const double* __restrict__ Lw, int d, int mv,
+                                            const double* __restrict__ X, double* __restrict__ Z,
+                                            int64_t Np, int64_t c0) {
+  const int c = threadIdx.x;
+  if (c < mv) {
+    for (int i = 0; i < d; ++i) {
+      double r = X[i * Np + c0 + c] - mu[i];
+      for (int j = 0; j < i; ++j) r -= Lw[i * d + j] * Z[j * Np + c0 + c];
+      Z[i * Np + c0 + c] = r / Lw[i * d + i];
+    }
+  }
+  __syncthreads();
+}
+
 __device__ __forceinline__ double lt_dot(const double* __restrict__ Lw, int d, int i,
                                 const double* __restrict__ G, int64_t Np, int64_t ch) {
   double v = 0;  // (L^T g)_i = sum_{j >= i} L[j][i] g_j
@@ -398,6 +415,7 @@ __device__ __forceinline__ void mh_tile(const KArgs& a, char* smem, typename P::
   const int64_t Np = S.Np;
   int* inbox = (int*)(smem + a.lds.mi);
   int* flag = inbox + 2 * M;
+  tile_whiten(a.wh.mu, a.wh.L, d, mv, S.x, S.z, Np, c0);
   for (int e = tid; e < d * M; e += kThreads) {
     const int i = e / M, c = e % M;
     if (c >= mv) continue;
@@ -432,6 +450,7 @@ __device__ __forceinline__ void mala_tile(const KArgs& a, char* smem, typename P
   int* inbox = (int*)(smem + a.lds.mi);
   int* flag = inbox + 2 * M;
   const double sq = sqrt(2.0 * eps);
+  tile_whiten(a.wh.mu, Lw, d, mv, S.x, S.z, Np, c0);
   for (int e = tid; e < d * M; e += kThreads) {
     const int i = e / M, c = e % M;
     if (c >= mv) continue;
@@ -483,6 +502,7 @@ __device__ __forceinline__ void hmc_tile(const KArgs& a, char* smem, typename P:
   int* flag = inbox + 2 * M;
   double* h0 = (double*)(smem + a.lds.md);
   const double he = 0.5 * eps;
+  tile_whiten(a.wh.mu, Lw, d, mv, S.x, S.z, Np, c0);
   // momentum, copies of the start point, whitened start gradient
   for (int e = tid; e < d * M; e += kThreads) {
     const int i = e / M, c = e % M;

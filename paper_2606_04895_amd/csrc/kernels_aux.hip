@@ -166,15 +166,16 @@ __global__ void moments_partial_kernel(const float* rec, const double* xs, int64
   }
 }
 
-// Cholesky-Banachiewicz of a (d x d, row-major) into L; false if a pivot is not > 0.
-__device__ bool chol(const double* a, double* L, int d) {
+// Cholesky-Banachiewicz of a (d x d, row-major) into L; false if a pivot is not finite and
+// above `floor` (numerical positive definiteness).
+__device__ bool chol(const double* a, double* L, int d, double floor) {
   for (int i = 0; i < d * d; ++i) L[i] = 0;
   for (int i = 0; i < d; ++i) {
     for (int j = 0; j <= i; ++j) {
       double s = a[i * d + j];
       for (int k = 0; k < j; ++k) s -= L[i * d + k] * L[j * d + k];
       if (i == j) {
-        if (!(s > 0.0) || !isfinite(s)) return false;
+        if (!(s > floor) || !isfinite(s)) return false;
         L[i * d + i] = sqrt(s);
       } else {
         L[i * d + j] = s / L[j * d + j];
@@ -213,16 +214,18 @@ __global__ void moments_final_kernel(const double* part, int nblocks, int64_t co
       const double c = 0.5 * (S[i * d + j] + S[j * d + i]);
       S[i * d + j] = S[j * d + i] = c;
     }
-  double jit = 0;
-  bool ok = chol(S, Lt, d);
+  double jit = 0, scale = 0;
+  for (int i = 0; i < d; ++i) scale += S[i * d + i];
+  scale /= d;
+  const double floor = isfinite(scale) ? 1e-12 * scale : 0.0;  // pivot floor
+  bool ok = chol(S, Lt, d, floor);
   if (!ok) {
-    double scale = 0;
-    for (int i = 0; i < d; ++i) scale += S[i * d + i];
-    scale /= d;
+    double S0[kMaxD];
+    for (int i = 0; i < d; ++i) S0[i] = S[i * d + i];
     for (double lam = 1e-10; lam <= 1e-2 * (1 + 1e-12) && !ok; lam *= 10.0) {
-      for (int i = 0; i < d; ++i) S[i * d + i] += lam * scale - jit;
       jit = lam * scale;
-      ok = chol(S, Lt, d);
+      for (int i = 0; i < d; ++i) S[i * d + i] = S0[i] + jit;
+      ok = chol(S, Lt, d, floor);
     }
   }
   if (!ok) {

@@ -29,16 +29,19 @@
 namespace best {
 
 #ifndef BEST_PREFETCH
-#define BEST_PREFETCH 4
+#define BEST_PREFETCH 8
 #endif
 #ifndef BEST_RG_MAX
 #define BEST_RG_MAX 4
 #endif
-constexpr int kPrefetch = BEST_PREFETCH;  // k-steps of weight fragments in flight per wave
+// k-steps of weight fragments in flight per wave (halved for the widest chain tiles and
+// for FP64, whose accumulators need the registers)
+constexpr int kPrefetch = BEST_PREFETCH;
 constexpr int kRgMax = BEST_RG_MAX;       // row tiles per register group
 
 struct MlpParams {
   int d, H, nh;
+  int lds_h;         // 1: saved activations stay in LDS (GEMM type), 0: global scratch
   const void* wf;    // T: fragment-ordered W_l, l = 2..nh, H*H each
   const void* wb;    // T: fragment-ordered W_l^T, l = 2..nh
   const void* w1;    // vec: [H][d]
@@ -55,10 +58,15 @@ struct MlpExport {
   int mvalid;
 };
 
+// LDS buffers of the tile engine.  With lds_h the activations h_1..h_L keep one slot each
+// (act + (l-1) M H, fragment order, GEMM type) and two further buffers hold deltas; without
+// it `act` holds two ping-pong buffers that the deltas reuse after the forward pass, and
+// the activations are saved to the per-workgroup global scratch.
 template <class P>
 struct MlpSmem {
-  typename P::T* buf0;   // M*H
-  typename P::T* buf1;   // M*H
+  typename P::T* act;    // activation slots / ping-pong buffers
+  typename P::T* dlt0;   // delta buffers (M*H each)
+  typename P::T* dlt1;
   typename P::vec* th;   // [M][d] input t
   typename P::vec* gth;  // [M][d] d out / d t
   typename P::acc* red;  // [kWaves][M][d] partial sums
@@ -80,7 +88,8 @@ __device__ __forceinline__ void gemm_group(const typename P::T* __restrict__ A, 
   // this hides the L2 latency that a load-then-use loop exposes at every k-step.
   using frag = typename P::frag;
   using accv = typename P::accv;
-  constexpr int D = kPrefetch;
+  constexpr int D = (MT >= 4 || sizeof(typename P::acc) == 8) ? (kPrefetch > 4 ? 4 : kPrefetch)
+                                                               : kPrefetch;
   const int lane = threadIdx.x & 63;
   accv acc[RG][MT];
 #pragma unroll
@@ -151,10 +160,56 @@ __device__ __forceinline__ typename P::acc* hsave_at(typename P::acc* base, int 
   return base + ((((int64_t)layer * RT + rt) * MT + ct) * 64 + lane) * 4;
 }
 
-// Forward pass: fills the activation scratch and s.out[c] (incl. b_out).
+// Buffers of the tile engine for a given storage mode.
+template <class P, int MT>
+__device__ __forceinline__ MlpSmem<P> mlp_smem(char* base, const MlpParams& mp) {
+  constexpr int M = 16 * MT;
+  MlpSmem<P> s;
+  const int64_t MH = (int64_t)M * mp.H;
+  s.act = (typename P::T*)base;
+  if (mp.lds_h) {
+    s.dlt0 = s.act + mp.nh * MH;
+    s.dlt1 = s.dlt0 + MH;
+  } else {
+    s.dlt0 = s.act + ((mp.nh - 1) & 1) * MH;
+    s.dlt1 = s.act + (mp.nh & 1) * MH;
+  }
+  return s;
+}
+
+// Output buffer of layer l (1-based).
+template <class P, int MT>
+__device__ __forceinline__ typename P::T* layer_buf(const MlpSmem<P>& s, const MlpParams& mp,
+                                                    int l) {
+  const int64_t MH = (int64_t)16 * MT * mp.H;
+  return s.act + (mp.lds_h ? (l - 1) : ((l - 1) & 1)) * MH;
+}
+
+// The saved activation h_l of this lane's D-tile slot r at row j of chain c.
+template <class P, int MT>
+__device__ __forceinline__ void load_h(const MlpSmem<P>& s, const MlpParams& mp,
+                                       typename P::acc* __restrict__ hsave, int l, int rt,
+                                       int ct, typename P::acc h[4]) {
+  using acc = typename P::acc;
+  const int lane = threadIdx.x & 63, g = lane >> 4, cl = lane & 15;
+  const int KS = mp.H / P::KSTEP, RT = mp.H / 16;
+  if (mp.lds_h) {
+    const typename P::T* b = layer_buf<P, MT>(s, mp, l);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) h[r] = (acc)b[lds_off<P>(rt * 16 + P::drow(g, r), ct * 16 + cl, KS)];
+  } else {
+    const acc* hp = hsave_at<P, MT>(hsave, l - 1, RT, rt, ct, lane);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) h[r] = __builtin_nontemporal_load(hp + r);
+  }
+}
+
+// Forward pass.  Writes s.out[c] (incl. b_out).  If fuse_delta, the last layer's epilogue
+// also writes delta_L = w_out (1 - h_L^2) (upstream 1) into s.dlt0 for mlp_backward.
 template <class P, int MT>
 __device__ __forceinline__ void mlp_forward(const MlpParams& mp, const MlpSmem<P>& s,
-                            typename P::acc* __restrict__ hsave, const MlpExport* ex) {
+                                            typename P::acc* __restrict__ hsave,
+                                            const MlpExport* ex, bool fuse_delta) {
   using T = typename P::T;
   using acc = typename P::acc;
   using vec = typename P::vec;
@@ -166,6 +221,43 @@ __device__ __forceinline__ void mlp_forward(const MlpParams& mp, const MlpSmem<P
   const vec* __restrict__ W1 = (const vec*)mp.w1;
   const acc* __restrict__ Bs = (const acc*)mp.bias;
   const acc* __restrict__ Wo = (const acc*)mp.wout;
+  acc po[MT];
+#pragma unroll
+  for (int ct = 0; ct < MT; ++ct) po[ct] = 0;
+
+  // epilogue shared by every layer: save h_l, feed layer l+1, and at the last layer the
+  // output dot product and (optionally) delta_L
+  auto finish = [&](int l, int rt, int ct, const acc hv[4]) {
+    const int c = ct * 16 + cl;
+    const bool last = (l == nh);
+    if (mp.lds_h || !last) {
+      T* ob = layer_buf<P, MT>(s, mp, l);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) ob[lds_off<P>(rt * 16 + P::drow(g, r), c, KS)] = (T)hv[r];
+    }
+    if (!mp.lds_h) {
+      acc* hp = hsave_at<P, MT>(hsave, l - 1, RT, rt, ct, lane);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) __builtin_nontemporal_store(hv[r], hp + r);
+    }
+    if (last) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) po[ct] += Wo[rt * 16 + P::drow(g, r)] * hv[r];
+      if (fuse_delta && nh > 1) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int j = rt * 16 + P::drow(g, r);
+          s.dlt0[lds_off<P>(j, c, KS)] = (T)(Wo[j] * ((acc)1 - hv[r] * hv[r]));
+        }
+      }
+    }
+    if (ex && c < ex->mvalid) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        ex->h[((int64_t)(l - 1) * H + rt * 16 + P::drow(g, r)) * ex->ldb + ex->col0 + c] =
+            (float)hv[r];
+    }
+  };
 
   // ---- layer 1: K = d on the vector ALUs ----
   for (int rr = 0; rr < RTW; ++rr) {
@@ -180,65 +272,27 @@ __device__ __forceinline__ void mlp_forward(const MlpParams& mp, const MlpSmem<P
         for (int i = 0; i < d; ++i) y += (acc)W1[j * d + i] * (acc)s.th[c * d + i];
         hv[r] = act_tanh(y);
       }
-      acc* hp = hsave_at<P, MT>(hsave, 0, RT, rt, ct, lane);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) hp[r] = hv[r];
-      if (nh > 1) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) s.buf0[lds_off<P>(rt * 16 + P::drow(g, r), c, KS)] = (T)hv[r];
-      }
-      if (ex && c < ex->mvalid) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          ex->h[(int64_t)(rt * 16 + P::drow(g, r)) * ex->ldb + ex->col0 + c] = (float)hv[r];
-      }
+      finish(1, rt, ct, hv);
     }
   }
   __syncthreads();
 
   // ---- hidden layers 2..nh: MFMA GEMMs ----
   for (int l = 2; l <= nh; ++l) {
-    const T* Bin = (l & 1) ? s.buf1 : s.buf0;
-    T* Bout = (l & 1) ? s.buf0 : s.buf1;
+    const T* Bin = layer_buf<P, MT>(s, mp, l - 1);
     const T* A = (const T*)mp.wf + (int64_t)(l - 2) * H * H;
     const acc* bl = Bs + (int64_t)(l - 1) * H;
-    const bool write_lds = l < nh;
     auto epi = [&](int rt, int ct, const accv& v) {
-      const int c = ct * 16 + cl;
       acc hv[4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) hv[r] = act_tanh((acc)v[r] + bl[rt * 16 + P::drow(g, r)]);
-      acc* hp = hsave_at<P, MT>(hsave, l - 1, RT, rt, ct, lane);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) hp[r] = hv[r];
-      if (write_lds) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) Bout[lds_off<P>(rt * 16 + P::drow(g, r), c, KS)] = (T)hv[r];
-      }
-      if (ex && c < ex->mvalid) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          ex->h[((int64_t)(l - 1) * H + rt * 16 + P::drow(g, r)) * ex->ldb + ex->col0 + c] =
-              (float)hv[r];
-      }
+      finish(l, rt, ct, hv);
     };
     gemm_rows<P, MT>(A, KS, Bin, wv * RTW, RTW, epi);
     __syncthreads();
   }
 
-  // ---- output layer: out[c] = w_out . h_nh + b_out (fixed-order sums) ----
-  acc po[MT];
-#pragma unroll
-  for (int ct = 0; ct < MT; ++ct) po[ct] = 0;
-  for (int rr = 0; rr < RTW; ++rr) {
-    const int rt = wv * RTW + rr;
-#pragma unroll
-    for (int ct = 0; ct < MT; ++ct) {
-      const acc* hp = hsave_at<P, MT>(hsave, nh - 1, RT, rt, ct, lane);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) po[ct] += Wo[rt * 16 + P::drow(g, r)] * hp[r];
-    }
-  }
+  // ---- output layer: fixed-order sums of the per-lane partial dot products ----
 #pragma unroll
   for (int ct = 0; ct < MT; ++ct) {
     const acc v = sum_lane_groups(po[ct]);
@@ -253,12 +307,14 @@ __device__ __forceinline__ void mlp_forward(const MlpParams& mp, const MlpSmem<P
   __syncthreads();
 }
 
-// Backward pass (reverse mode).  Requires mlp_forward's scratch; s.up (or 1) is the
-// upstream gradient per chain.  If want_input_grad, writes s.gth[c][i] = d(up*out)/d t_i.
+// Backward pass (reverse mode).  s.up (or 1) is the upstream gradient per chain; if the
+// forward fused delta_L, s.up must be NULL.  If want_input_grad, writes
+// s.gth[c][i] = d(up * out)/d t_i.
 template <class P, int MT>
 __device__ __forceinline__ void mlp_backward(const MlpParams& mp, const MlpSmem<P>& s,
-                             typename P::acc* __restrict__ hsave, const MlpExport* ex,
-                             bool want_input_grad) {
+                                             typename P::acc* __restrict__ hsave,
+                                             const MlpExport* ex, bool want_input_grad,
+                                             bool delta_fused) {
   using T = typename P::T;
   using acc = typename P::acc;
   using vec = typename P::vec;
@@ -266,7 +322,7 @@ __device__ __forceinline__ void mlp_backward(const MlpParams& mp, const MlpSmem<
   constexpr int M = 16 * MT;
   const int tid = threadIdx.x, lane = tid & 63, g = lane >> 4, wv = tid >> 6, cl = lane & 15;
   const int d = mp.d, H = mp.H, nh = mp.nh;
-  const int KS = H / P::KSTEP, RTW = H / 64, RT = H / 16;
+  const int KS = H / P::KSTEP, RTW = H / 64;
   const vec* __restrict__ W1 = (const vec*)mp.w1;
   const acc* __restrict__ Wo = (const acc*)mp.wout;
 
@@ -286,45 +342,47 @@ __device__ __forceinline__ void mlp_backward(const MlpParams& mp, const MlpSmem<
     }
   };
 
-  // ---- delta_nh = up * w_out * (1 - h_nh^2) ----
-  for (int rr = 0; rr < RTW; ++rr) {
-    const int rt = wv * RTW + rr;
-    for (int ct = 0; ct < MT; ++ct) {
-      const int c = ct * 16 + cl;
-      const acc u = s.up ? s.up[c] : (acc)1;
-      const acc* hp = hsave_at<P, MT>(hsave, nh - 1, RT, rt, ct, lane);
-      acc dl[4];
+  // ---- delta_L = up * w_out * (1 - h_L^2), unless the forward epilogue wrote it ----
+  if (!delta_fused || nh == 1) {
+    for (int rr = 0; rr < RTW; ++rr) {
+      const int rt = wv * RTW + rr;
+      for (int ct = 0; ct < MT; ++ct) {
+        const int c = ct * 16 + cl;
+        const acc u = s.up ? s.up[c] : (acc)1;
+        acc hv[4], dl[4];
+        load_h<P, MT>(s, mp, hsave, nh, rt, ct, hv);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) dl[r] = u * Wo[rt * 16 + P::drow(g, r)] * ((acc)1 - hp[r] * hp[r]);
-      if (nh > 1) {
+        for (int r = 0; r < 4; ++r) dl[r] = u * Wo[rt * 16 + P::drow(g, r)] * ((acc)1 - hv[r] * hv[r]);
+        if (nh > 1) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) s.buf0[lds_off<P>(rt * 16 + P::drow(g, r), c, KS)] = (T)dl[r];
-      } else if (want_input_grad) {
-        input_grad_acc(rt, ct, dl);
-      }
-      if (ex && c < ex->mvalid) {
+          for (int r = 0; r < 4; ++r) s.dlt0[lds_off<P>(rt * 16 + P::drow(g, r), c, KS)] = (T)dl[r];
+        } else if (want_input_grad) {
+          input_grad_acc(rt, ct, dl);
+        }
+        if (ex && c < ex->mvalid) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-          ex->dl[((int64_t)(nh - 1) * H + rt * 16 + P::drow(g, r)) * ex->ldb + ex->col0 + c] =
-              (float)dl[r];
+          for (int r = 0; r < 4; ++r)
+            ex->dl[((int64_t)(nh - 1) * H + rt * 16 + P::drow(g, r)) * ex->ldb + ex->col0 + c] =
+                (float)dl[r];
+        }
       }
     }
+    __syncthreads();
   }
-  __syncthreads();
 
   // ---- hidden layers nh..2: D[k][c] = sum_j W_l^T[k][j] delta_l[j][c] ----
   for (int l = nh; l >= 2; --l) {
-    const bool in_buf0 = ((nh - l) & 1) == 0;
-    const T* Bin = in_buf0 ? s.buf0 : s.buf1;
-    T* Bout = in_buf0 ? s.buf1 : s.buf0;
+    const bool in0 = ((nh - l) & 1) == 0;
+    const T* Bin = in0 ? s.dlt0 : s.dlt1;
+    T* Bout = in0 ? s.dlt1 : s.dlt0;
     const T* A = (const T*)mp.wb + (int64_t)(l - 2) * H * H;
     const bool last = (l == 2);
     auto epi = [&](int rt, int ct, const accv& v) {
       const int c = ct * 16 + cl;
-      const acc* hp = hsave_at<P, MT>(hsave, l - 2, RT, rt, ct, lane);
-      acc dl[4];
+      acc hv[4], dl[4];
+      load_h<P, MT>(s, mp, hsave, l - 1, rt, ct, hv);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) dl[r] = (acc)v[r] * ((acc)1 - hp[r] * hp[r]);
+      for (int r = 0; r < 4; ++r) dl[r] = (acc)v[r] * ((acc)1 - hv[r] * hv[r]);
       if (!last) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) Bout[lds_off<P>(rt * 16 + P::drow(g, r), c, KS)] = (T)dl[r];

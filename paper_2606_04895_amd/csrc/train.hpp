@@ -66,9 +66,7 @@ __global__ __launch_bounds__(kThreads, 1) void train_tile_kernel(TrainArgs a) {
   constexpr int M = 16 * MT;
   const int tid = threadIdx.x, d = a.mp.d;
   acc* hsave = (acc*)a.hsave + (int64_t)blockIdx.x * a.hsave_stride;
-  MlpSmem<P> s;
-  s.buf0 = (typename P::T*)(smem + a.lds.big);
-  s.buf1 = s.buf0 + M * a.mp.H;
+  MlpSmem<P> s = mlp_smem<P, MT>(smem + a.lds.big, a.mp);
   s.th = (vec*)(smem + a.lds.th);
   s.gth = (vec*)(smem + a.lds.gth);
   s.red = (acc*)(smem + a.lds.red);
@@ -89,7 +87,7 @@ __global__ __launch_bounds__(kThreads, 1) void train_tile_kernel(TrainArgs a) {
     }
     __syncthreads();
     MlpExport ex{a.ex_h, a.ex_dl, a.B, c0, mv};
-    mlp_forward<P, MT>(a.mp, s, hsave, &ex);
+    mlp_forward<P, MT>(a.mp, s, hsave, &ex, false);
     if (tid < M) {
       double r = 0;
       if (tid < mv) r = (double)s.out[tid] - (double)a.y[a.perm[a.batch0 + c0 + tid]];
@@ -104,7 +102,7 @@ __global__ __launch_bounds__(kThreads, 1) void train_tile_kernel(TrainArgs a) {
       for (int c = 0; c < M; ++c) t += r2[c];
       a.loss_part[tile] = t;
     }
-    mlp_backward<P, MT>(a.mp, s, hsave, &ex, false);
+    mlp_backward<P, MT>(a.mp, s, hsave, &ex, false, false);
   }
 }
 

@@ -207,9 +207,9 @@ def test_resume_from_checkpoint_is_bitwise():
     xa = B.best_get_state(a)[0]
     b = B.best_init(prob, n_chains=64, precision="fp32", seed=4)
     B.best_step(b, "hmc", 3, eps=0.2, n_leapfrog=4)
-    x_mid = B.best_get_state(b)[0]
+    x_mid, lp_mid, g_mid = B.best_get_state(b)
     c = B.best_init(prob, n_chains=64, precision="fp32", seed=4)
-    B.best_set_state(c, x_mid)
+    B.best_set_state(c, x_mid, lp_mid, g_mid)
     B.best_set_step_counter(c, 3)
     B.best_step(c, "hmc", 3, eps=0.2, n_leapfrog=4)
     assert np.array_equal(B.best_get_state(c)[0], xa)
