@@ -25,8 +25,6 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"bf16": 2.5e15, "fp16": 2.5e15, "fp32": 157.3e12, "fp64": 78.6e12}
-TARGET_ACCEPT = {"mala": 0.57, "hmc": 0.8}
-EPS0 = {"mala": 0.5, "hmc": 0.3}
 
 
 def flops_per_eval(d, H, nh):
@@ -41,30 +39,12 @@ def gemm_flops_per_eval(H, nh):
 
 
 def run_chain(B, torch, prob, prec, sampler, n, warmup, steps, seed, n_leap):
-    ctx = B.best_init(prob, n_chains=n, precision=prec, seed=seed, init="uniform")
+    from paper_2606_04895_amd import driver
+
     d = prob["d"]
-    B.best_set_step_size(ctx, EPS0[sampler])
-    target = TARGET_ACCEPT[sampler]
-    kw = dict(n_leapfrog=n_leap)
-    t_adapt0 = time.perf_counter()
-    bounds = sorted(set([0, max(1, warmup // 4), max(1, warmup // 2), warmup]))
-    for a, b in zip(bounds[:-1], bounds[1:]):
-        w = b - a
-        rec = torch.empty((w, d, n), dtype=torch.float32, device="cuda")
-        B.best_step(ctx, sampler, w, record=rec, adapt_eps=True, target_accept=target, **kw)
-        keep = rec[w // 2:] if w >= 4 else rec
-        B.best_adapt(ctx, samples=keep.contiguous(), update_mean=True, finalize_da=True,
-                     reset_da=True, target_accept=target)
-        del rec
-    torch.cuda.synchronize()
-    t_adapt = time.perf_counter() - t_adapt0
-    rec = torch.empty((steps, d, n), dtype=torch.float32, device="cuda")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    st = B.best_step(ctx, sampler, steps, record=rec, **kw)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ess = B.best_ess(ctx, rec)
+    ctx = B.best_init(prob, n_chains=n, precision=prec, seed=seed, init="uniform")
+    t_adapt = driver.burn_in(ctx, sampler, warmup, d, n, n_leap=n_leap)
+    st, rec, wall, ess = driver.sample(ctx, sampler, steps, d, n, n_leap=n_leap)
     mean = rec.double().mean(dim=(0, 2)).cpu().numpy()
     out = dict(wall_s=wall, kernel_ms=st["ms"], evals=st["evals"],
                accept=st["accepted"] / (steps * n), eps=st["eps"], adapt_s=t_adapt,

@@ -91,7 +91,7 @@ typedef struct {
 /* The target (see the top of this file).  All pointers are host pointers; the problem is
  * deep-copied by best_init.  mlp_params is the flat vector
  *   [W1 (H x d), b1 (H), W2 (H x H), b2, ..., W_L (H x H), b_L, w_out (H), b_out]
- * of length best_mlp_nparams(d, width, n_hidden).  width must be a multiple of 64 and at
+ * of length best_mlp_nparams(d, width, n_hidden).  width must be a multiple of 128 and at
  * most 2048; 1 <= d <= 32; 1 <= n_hidden <= 16. */
 typedef struct {
   int32_t d;
@@ -220,7 +220,8 @@ int best_ess(best_ctx *h, const float *record, int64_t T, double *ess_out);
 /* ---- learned emulator (training on plain-model pairs) ---- */
 
 /* A trainer owns an FP64 master copy of the MLP parameters and Adam moments on the device.
- * Training minimises mean_c (MLP(t_c) - y_c)^2 with Adam (b1 0.9, b2 0.999, eps 1e-8). */
+ * Training minimises mean_c (MLP(t_c) - y_c)^2 with Adam (b1 0.9, b2 0.999, eps 1e-8).
+ * width: a multiple of 128 in [128, 2048]; precision FP32, FP16 or BF16. */
 int best_trainer_create(best_trainer **out, int32_t d, int32_t width, int32_t n_hidden,
                         const double *init_params, int32_t precision, void *stream);
 void best_trainer_destroy(best_trainer *t);

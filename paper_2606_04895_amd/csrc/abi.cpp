@@ -19,7 +19,7 @@ namespace best {
   hipError_t launch_eval_##suf(int, const KArgs&, int, size_t, hipStream_t);                 \
   hipError_t launch_train_tile_##suf(int, const TrainArgs&, int, size_t, hipStream_t);       \
   hipError_t launch_pack_##suf(const double*, int, int, int, void*, void*, void*, void*, void*, \
-                               hipStream_t);
+                               void*, hipStream_t);
 BEST_DECL_PREC(f64)
 BEST_DECL_PREC(f32)
 BEST_DECL_PREC(f16)
@@ -51,12 +51,12 @@ hipError_t launch_train_tile(int prec, int MT, const TrainArgs& a, int grid, siz
   }
 }
 hipError_t launch_pack(int prec, const double* flat, int d, int H, int nh, void* wf, void* wb,
-                       void* w1, void* bias, void* wout, hipStream_t s) {
+                       void* w1f, void* w1t, void* bias, void* wout, hipStream_t s) {
   switch (prec) {
-    case BEST_FP64: return launch_pack_f64(flat, d, H, nh, wf, wb, w1, bias, wout, s);
-    case BEST_FP32: return launch_pack_f32(flat, d, H, nh, wf, wb, w1, bias, wout, s);
-    case BEST_FP16: return launch_pack_f16(flat, d, H, nh, wf, wb, w1, bias, wout, s);
-    default: return launch_pack_bf16(flat, d, H, nh, wf, wb, w1, bias, wout, s);
+    case BEST_FP64: return launch_pack_f64(flat, d, H, nh, wf, wb, w1f, w1t, bias, wout, s);
+    case BEST_FP32: return launch_pack_f32(flat, d, H, nh, wf, wb, w1f, w1t, bias, wout, s);
+    case BEST_FP16: return launch_pack_f16(flat, d, H, nh, wf, wb, w1f, w1t, bias, wout, s);
+    default: return launch_pack_bf16(flat, d, H, nh, wf, wb, w1f, w1t, bias, wout, s);
   }
 }
 }  // namespace best
@@ -100,9 +100,39 @@ struct Arena {
 int tsize(int prec) { return prec == BEST_FP64 ? 8 : prec == BEST_FP32 ? 4 : 2; }
 int vasize(int prec) { return prec == BEST_FP64 ? 8 : 4; }
 int mt_max(int prec) { return prec == BEST_FP64 ? 2 : 4; }
+// Input layer: FP64 MFMA (k-step 8) for the FP64 path, FP32 MFMA (k-step 16) otherwise.
+int in_kstep(int prec) { return prec == BEST_FP64 ? 8 : 16; }
+int in_size(int prec) { return prec == BEST_FP64 ? 8 : 4; }
+int in_ksteps(int prec, int d) { return (d + in_kstep(prec) - 1) / in_kstep(prec); }
+int grad_rtiles(int d) { return (d + 15) / 16; }
 
 LdsLayout layout_for(int prec, int MT, int H, int d, int nh, int lds_h) {
-  return lds_layout(16 * MT, H, d, nh, lds_h, tsize(prec), vasize(prec), vasize(prec));
+  return lds_layout(16 * MT, H, d, nh, lds_h, tsize(prec), vasize(prec), vasize(prec),
+                    in_ksteps(prec, d) * in_kstep(prec), in_size(prec));
+}
+
+// Packed input-layer weights: W_1 for the input GEMM and W_1^T for the input gradient.
+size_t w1f_bytes(int prec, int H, int d) {
+  return (size_t)H * in_ksteps(prec, d) * in_kstep(prec) * in_size(prec);
+}
+size_t w1t_bytes(int prec, int H, int d) { return (size_t)16 * grad_rtiles(d) * H * tsize(prec); }
+
+MlpParams make_mlp_params(int prec, int d, int H, int nh, int lds_h, void* wf, void* wb,
+                          void* w1f, void* w1t, void* bias, void* wout) {
+  MlpParams mp{};
+  mp.d = d;
+  mp.H = H;
+  mp.nh = nh;
+  mp.lds_h = lds_h;
+  mp.ks1 = in_ksteps(prec, d);
+  mp.rti = grad_rtiles(d);
+  mp.wf = wf;
+  mp.wb = wb;
+  mp.w1f = w1f;
+  mp.w1t = w1t;
+  mp.bias = bias;
+  mp.wout = wout;
+  return mp;
 }
 
 // Packed hidden weights (forward and transposed copies) in the GEMM type.
@@ -129,7 +159,8 @@ struct best_ctx {
   MlpParams mp{};
   State st{};
   double *mu = nullptr, *L = nullptr, *da = nullptr, *flat = nullptr;
-  void *wf = nullptr, *wb = nullptr, *w1 = nullptr, *bias = nullptr, *wout = nullptr;
+  void *wf = nullptr, *wb = nullptr, *w1f = nullptr, *w1t = nullptr, *bias = nullptr,
+       *wout = nullptr;
   void* hsave = nullptr;
   int64_t hsave_stride = 0;
   int grid_cap = 0;
@@ -255,8 +286,8 @@ static int validate_problem(best_ctx* h, const best_problem* p, const best_confi
   for (int i = 0; i < d; ++i)
     if (!(p->lower[i] < p->upper[i]) || !std::isfinite(p->lower[i]) || !std::isfinite(p->upper[i]))
       return fail(h, BEST_EINVAL, "need finite lower[i] < upper[i]");
-  if (p->width < 64 || p->width > 2048 || p->width % 64)
-    return fail(h, BEST_EINVAL, "width must be a multiple of 64 in [64, 2048]");
+  if (p->width < 128 || p->width > 2048 || p->width % 128)
+    return fail(h, BEST_EINVAL, "width must be a multiple of 128 in [128, 2048]");
   if (p->n_hidden < 1 || p->n_hidden > 16) return fail(h, BEST_EINVAL, "n_hidden must be in [1, 16]");
   if (p->gauss_coef != 0.0 && (!p->gauss_mean || !p->gauss_prec))
     return fail(h, BEST_EINVAL, "gauss_mean/gauss_prec is NULL");
@@ -372,19 +403,13 @@ static int alloc_mlp(best_ctx* h) {
   const size_t nW = (size_t)std::max(nh - 1, 1) * H * H;
   HIPCHK(h, m.alloc((char**)&h->wf, nW * ts));
   HIPCHK(h, m.alloc((char**)&h->wb, nW * ts));
-  HIPCHK(h, m.alloc((char**)&h->w1, (size_t)H * d * va));
+  HIPCHK(h, m.alloc((char**)&h->w1f, w1f_bytes(h->prec, H, d)));
+  HIPCHK(h, m.alloc((char**)&h->w1t, w1t_bytes(h->prec, H, d)));
   HIPCHK(h, m.alloc((char**)&h->bias, (size_t)nh * H * va));
   HIPCHK(h, m.alloc((char**)&h->wout, (size_t)(H + 1) * va));
   HIPCHK(h, m.alloc(&h->flat, (size_t)mlp_nparams_impl(d, H, nh)));
-  h->mp.d = d;
-  h->mp.H = H;
-  h->mp.nh = nh;
-  h->mp.lds_h = h->lds_h;
-  h->mp.wf = h->wf;
-  h->mp.wb = h->wb;
-  h->mp.w1 = h->w1;
-  h->mp.bias = h->bias;
-  h->mp.wout = h->wout;
+  h->mp = make_mlp_params(h->prec, d, H, nh, h->lds_h, h->wf, h->wb, h->w1f, h->w1t, h->bias,
+                          h->wout);
   return BEST_OK;
 }
 
@@ -392,8 +417,8 @@ static int load_mlp(best_ctx* h, const double* params) {
   const int64_t np = mlp_nparams_impl(h->d, h->H, h->nh);
   if (!finite_all(params, np)) return fail(h, BEST_EINVAL, "MLP parameters must be finite");
   HIPCHK(h, hipMemcpyAsync(h->flat, params, np * sizeof(double), hipMemcpyHostToDevice, h->stream));
-  HIPCHK(h, launch_pack(h->prec, h->flat, h->d, h->H, h->nh, h->wf, h->wb, h->w1, h->bias,
-                        h->wout, h->stream));
+  HIPCHK(h, launch_pack(h->prec, h->flat, h->d, h->H, h->nh, h->wf, h->wb, h->w1f, h->w1t,
+                        h->bias, h->wout, h->stream));
   return BEST_OK;
 }
 
@@ -873,7 +898,8 @@ struct best_trainer {
   int64_t np = 0, t = 0;
   Arena mem;
   double *p = nullptr, *m = nullptr, *v = nullptr, *g = nullptr;
-  void *wf = nullptr, *wb = nullptr, *w1 = nullptr, *bias = nullptr, *wout = nullptr;
+  void *wf = nullptr, *wb = nullptr, *w1f = nullptr, *w1t = nullptr, *bias = nullptr,
+       *wout = nullptr;
   MlpParams mp{};
   LdsLayout lds{};
   void* hsave = nullptr;
@@ -954,7 +980,7 @@ int best_trainer_create(best_trainer** out, int32_t d, int32_t width, int32_t n_
                         const double* init_params, int32_t precision, void* stream) {
   if (!out) return BEST_EINVAL;
   *out = nullptr;
-  if (d < 1 || d > kMaxD || width < 64 || width > 2048 || width % 64 || n_hidden < 1 ||
+  if (d < 1 || d > kMaxD || width < 128 || width > 2048 || width % 128 || n_hidden < 1 ||
       n_hidden > 16 || !init_params)
     return BEST_EINVAL;
   if (precision != BEST_FP32 && precision != BEST_FP16 && precision != BEST_BF16)
@@ -990,7 +1016,8 @@ int best_trainer_create(best_trainer** out, int32_t d, int32_t width, int32_t n_
       t->mem.alloc(&t->g, t->np) != hipSuccess ||
       t->mem.alloc((char**)&t->wf, nW * ts) != hipSuccess ||
       t->mem.alloc((char**)&t->wb, nW * ts) != hipSuccess ||
-      t->mem.alloc((char**)&t->w1, (size_t)width * d * 4) != hipSuccess ||
+      t->mem.alloc((char**)&t->w1f, w1f_bytes(precision, width, d)) != hipSuccess ||
+      t->mem.alloc((char**)&t->w1t, w1t_bytes(precision, width, d)) != hipSuccess ||
       t->mem.alloc((char**)&t->bias, (size_t)n_hidden * width * 4) != hipSuccess ||
       t->mem.alloc((char**)&t->wout, (size_t)(width + 1) * 4) != hipSuccess ||
       t->mem.alloc(&t->loss_steps, 1 << 16) != hipSuccess)
@@ -999,7 +1026,8 @@ int best_trainer_create(best_trainer** out, int32_t d, int32_t width, int32_t n_
   if (hipMemsetAsync(t->m, 0, t->np * 8, t->stream) != hipSuccess ||
       hipMemsetAsync(t->v, 0, t->np * 8, t->stream) != hipSuccess)
     return bail(tfail(t, BEST_EHIP, "memset"));
-  t->mp = MlpParams{d, width, n_hidden, lds_h, t->wf, t->wb, t->w1, t->bias, t->wout};
+  t->mp = make_mlp_params(precision, d, width, n_hidden, lds_h, t->wf, t->wb, t->w1f, t->w1t,
+                          t->bias, t->wout);
   t->grid_cap = t->n_cu * std::max(1, std::min(2, kLdsMax / t->lds.total));
   t->hsave_stride = (int64_t)n_hidden * width * 16 * t->MT;
   if (t->mem.alloc((char**)&t->hsave, (size_t)t->grid_cap * t->hsave_stride * 4) != hipSuccess)
@@ -1015,8 +1043,8 @@ int best_trainer_create(best_trainer** out, int32_t d, int32_t width, int32_t n_
   for (int l = 2; l <= n_hidden; ++l) t->w_offs.push_back(base + (l - 2) * blk);
   if (t->mem.upload(&t->offs, offs.data(), offs.size(), t->stream) != hipSuccess)
     return bail(tfail(t, BEST_ENOMEM, "offsets"));
-  if (hipError_t e = launch_pack(precision, t->p, d, width, n_hidden, t->wf, t->wb, t->w1,
-                                 t->bias, t->wout, t->stream))
+  if (hipError_t e = launch_pack(precision, t->p, d, width, n_hidden, t->wf, t->wb, t->w1f,
+                                 t->w1t, t->bias, t->wout, t->stream))
     return bail(tfail(t, BEST_EHIP, std::string("pack: ") + hipGetErrorString(e)));
   if (hipStreamSynchronize(t->stream) != hipSuccess) return bail(tfail(t, BEST_EHIP, "sync"));
   *out = t;
@@ -1069,8 +1097,8 @@ int best_train_epoch(best_trainer* t, const float* t_in, const float* y, int64_t
     const double s = (double)(step0 + i);
     const double lr = lr1 + 0.5 * (lr0 - lr1) * (1.0 + std::cos(M_PI * s / (double)total_steps));
     THIPCHK(t, launch_adam(t->p, t->m, t->v, t->g, t->np, lr, b1, b2, eps, c1, c2, t->stream));
-    THIPCHK(t, launch_pack(t->prec, t->p, t->d, t->H, t->nh, t->wf, t->wb, t->w1, t->bias,
-                           t->wout, t->stream));
+    THIPCHK(t, launch_pack(t->prec, t->p, t->d, t->H, t->nh, t->wf, t->wb, t->w1f, t->w1t,
+                           t->bias, t->wout, t->stream));
   }
   if (mean_loss) {
     std::vector<double> ls(nb);

@@ -12,7 +12,7 @@ constexpr int kEssLB = 128;  // lags per autocovariance pass
 hipError_t launch_step(int prec, int MT, const KArgs& a, int grid, size_t lds, hipStream_t s);
 hipError_t launch_eval(int prec, int MT, const KArgs& a, int grid, size_t lds, hipStream_t s);
 hipError_t launch_pack(int prec, const double* flat, int d, int H, int nh, void* wf, void* wb,
-                       void* w1, void* bias, void* wout, hipStream_t s);
+                       void* w1f, void* w1t, void* bias, void* wout, hipStream_t s);
 hipError_t launch_train_tile(int prec, int MT, const TrainArgs& a, int grid, size_t lds,
                              hipStream_t s);
 

@@ -12,8 +12,9 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 namespace best {
 
-constexpr int kThreads = 256;  // 4 wave64 per workgroup, one per SIMD of a CU
-constexpr int kWaves = 4;
+constexpr int kThreads = 512;  // 8 wave64 per tile workgroup, two per SIMD of a CU
+constexpr int kWaves = 8;
+constexpr int kAuxThreads = 256;  // block size of the small reduction kernels
 constexpr int kMaxD = 32;
 
 // ---------------------------------------------------------------------------------------

@@ -46,15 +46,18 @@ __host__ __device__ inline int align16(int v) { return (v + 15) & ~15; }
 
 // Union region: {activation slots or ping-pong buffers + delta buffers} during the MLP,
 // {R, PR, plain results, plain scratch} during the FP64 assembly.
+// The input buffer holds M x k1 values of isize bytes (d padded to the input layer's
+// k-step).
 __host__ __device__ inline LdsLayout lds_layout(int M, int H, int d, int nh, int lds_h,
-                                               int tsize, int vsize, int asize) {
+                                               int tsize, int vsize, int asize, int k1,
+                                               int isize) {
   LdsLayout L;
   const int mlp_bytes = (lds_h ? nh + 2 : 2) * M * H * tsize;
   const int asm_bytes = 8 * (2 * d * M + M + M * d + kMaxD + 3 * kMaxTerms + kWaves * 32);
   L.big = 0;
   int o = align16(mlp_bytes > asm_bytes ? mlp_bytes : asm_bytes);
   L.th = o;
-  o = align16(o + M * d * vsize);
+  o = align16(o + M * k1 * isize);
   L.gth = o;
   o = align16(o + M * d * vsize);
   L.red = o;
@@ -213,12 +216,13 @@ __device__ __forceinline__ void eval_tile(const KArgs& a, char* smem, typename P
                           bool grad, bool box) {
   using acc = typename P::acc;
   using vec = typename P::vec;
+  using IP = typename InPrec<P>::type;
   constexpr int M = 16 * MT;
   const Target& tg = a.tg;
   const int tid = threadIdx.x, d = tg.d;
   const LdsLayout& L = a.lds;
   MlpSmem<P> s = mlp_smem<P, MT>(smem + L.big, a.mp);
-  s.th = (vec*)(smem + L.th);
+  s.thf = (typename IP::T*)(smem + L.th);
   s.gth = (vec*)(smem + L.gth);
   s.red = (acc*)(smem + L.red);
   s.out = (acc*)(smem + L.out);
@@ -226,10 +230,13 @@ __device__ __forceinline__ void eval_tile(const KArgs& a, char* smem, typename P
   int* inbox = (int*)(smem + L.mi);
   int* intrain = inbox + M;
 
-  for (int e = tid; e < M * d; e += kThreads) {
-    const int c = e / d, i = e % d;
-    const double xv = c < mv ? X[i * pitch + c0 + c] : tg.in_center[i];
-    s.th[e] = (vec)((xv - tg.in_center[i]) * tg.in_invscale[i]);
+  // normalised inputs t = (x - center) * invscale; padding chains and components are 0
+  const int K1 = a.mp.ks1 * IP::KSTEP;
+  for (int e = tid; e < M * K1; e += kThreads) {
+    const int c = e / K1, i = e % K1;
+    double v = 0.0;
+    if (i < d && c < mv) v = (X[i * pitch + c0 + c] - tg.in_center[i]) * tg.in_invscale[i];
+    store_t<P>(s, a.mp, c, i, v);
   }
   for (int c = tid; c < M; c += kThreads) {
     int ib = 1, it = 1;

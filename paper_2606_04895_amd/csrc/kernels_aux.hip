@@ -49,7 +49,7 @@ __device__ double block_sum(double v, double* sh) {
   const int tid = threadIdx.x;
   sh[tid] = v;
   __syncthreads();
-  for (int s = kThreads / 2; s > 0; s >>= 1) {
+  for (int s = kAuxThreads / 2; s > 0; s >>= 1) {
     if (tid < s) sh[tid] += sh[tid + s];
     __syncthreads();
   }
@@ -61,9 +61,9 @@ __device__ double block_sum(double v, double* sh) {
 // ---- dual averaging (Hoffman & Gelman 2014) on the chain-mean acceptance -------------
 // da = [mu, h_bar, log_eps_bar, m, eps, delta, gamma, t0, kappa]
 __global__ void da_update_kernel(const double* step_prob, int64_t N, double* da) {
-  __shared__ double sh[kThreads];
+  __shared__ double sh[kAuxThreads];
   double v = 0;
-  for (int64_t c = threadIdx.x; c < N; c += kThreads) v += step_prob[c];
+  for (int64_t c = threadIdx.x; c < N; c += kAuxThreads) v += step_prob[c];
   const double mean = block_sum(v, sh) / (double)N;
   if (threadIdx.x == 0) {
     const double m = da[3] + 1.0;
@@ -80,9 +80,9 @@ __global__ void da_update_kernel(const double* step_prob, int64_t N, double* da)
 
 // ---- per-call statistics: [accepted, nonfinite, oob] int64 + [sum_prob] -----------------
 __global__ void stats_kernel(State S, int64_t* out_i, double* out_d) {
-  __shared__ double sh[kThreads];
+  __shared__ double sh[kAuxThreads];
   double a = 0, nf = 0, oob = 0, sp = 0;
-  for (int64_t c = threadIdx.x; c < S.N; c += kThreads) {
+  for (int64_t c = threadIdx.x; c < S.N; c += kAuxThreads) {
     a += S.n_acc[c];
     nf += S.n_nonfinite[c];
     oob += S.n_oob[c];
@@ -135,7 +135,7 @@ __global__ void moments_partial_kernel(const float* rec, const double* xs, int64
     __syncthreads();
     const int cnt = (int)min((int64_t)kChunk, b1 - base);
     for (int k = 0; k < 4; ++k) {
-      const int p = threadIdx.x + k * kThreads;
+      const int p = threadIdx.x + k * kAuxThreads;
       if (p >= np) break;
       int i, j;
       if (p < d) {
@@ -161,7 +161,7 @@ __global__ void moments_partial_kernel(const float* rec, const double* xs, int64
     __syncthreads();
   }
   for (int k = 0; k < 4; ++k) {
-    const int p = threadIdx.x + k * kThreads;
+    const int p = threadIdx.x + k * kAuxThreads;
     if (p < np) part[(int64_t)blockIdx.x * np + p] = accs[k];
   }
 }
@@ -194,7 +194,7 @@ __global__ void moments_final_kernel(const double* part, int nblocks, int64_t co
   __shared__ double Lt[kMaxD * kMaxD];
   __shared__ double sum[kMaxD + kMaxD * (kMaxD + 1) / 2];
   const int np = d + d * (d + 1) / 2;
-  for (int p = threadIdx.x; p < np; p += kThreads) {
+  for (int p = threadIdx.x; p < np; p += kAuxThreads) {
     double s = 0;
     for (int b = 0; b < nblocks; ++b) s += part[(int64_t)b * np + p];
     sum[p] = s;
@@ -266,7 +266,7 @@ __global__ void ess_chain_stats_kernel(const float* rec, int64_t T, int d, int64
 
 // Sum over the 64 chains of a block of sum_s y_s y_{s+t} for t in [lag0, lag0 + kEssLB).
 // grid = (ceil(N/64), d); LDS holds the two time windows of the block's chains.
-__global__ __launch_bounds__(kThreads) void ess_autocov_kernel(const float* rec,
+__global__ __launch_bounds__(kAuxThreads) void ess_autocov_kernel(const float* rec,
                                                                const double* mean, int64_t T,
                                                                int d, int64_t N, int64_t lag0,
                                                                double* part) {
@@ -329,7 +329,7 @@ __global__ void adam_kernel(double* p, double* m, double* v, const double* g, in
 
 // dW_l = delta_l h_{l-1}^T for l >= 2 on FP32 MFMA: A = delta [H][ldb], B = h [H][ldb],
 // K = batch.  Workgroup tile 64 x 64, wave w owns rows [16 w, 16 w + 16).
-__global__ __launch_bounds__(kThreads) void dw_gemm_kernel(const float* dl, const float* h,
+__global__ __launch_bounds__(kAuxThreads) void dw_gemm_kernel(const float* dl, const float* h,
                                                            int64_t ldb, int64_t B, int H,
                                                            double* gW) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, g = lane >> 4, cl = lane & 15;
@@ -380,9 +380,9 @@ __global__ void dsmall_kernel(const float* dl, const float* h, const float* th, 
 }
 
 __global__ void sum_kernel(const double* part, int n, double scale, double* out) {
-  __shared__ double sh[kThreads];
+  __shared__ double sh[kAuxThreads];
   double v = 0;
-  for (int i = threadIdx.x; i < n; i += kThreads) v += part[i];
+  for (int i = threadIdx.x; i < n; i += kAuxThreads) v += part[i];
   v = block_sum(v, sh);
   if (threadIdx.x == 0) *out = v * scale;
 }
@@ -391,12 +391,12 @@ __global__ void sum_kernel(const double* part, int n, double scale, double* out)
 // mode 0: sum a;  1: sum (a - s)^2;  2: max (a - b);  3: sum e, sum e^2 with e = exp(a - b - s)
 __global__ void reduce_partial_kernel(int mode, const double* a, const double* b, int64_t n,
                                       double s, double* part) {
-  __shared__ double sh[kThreads];
-  __shared__ double sh2[kThreads];
+  __shared__ double sh[kAuxThreads];
+  __shared__ double sh2[kAuxThreads];
   const int64_t per = (n + gridDim.x - 1) / gridDim.x;
   const int64_t i0 = blockIdx.x * per, i1 = min(n, i0 + per);
   double v = mode == 2 ? -INFINITY : 0.0, v2 = 0.0;
-  for (int64_t i = i0 + threadIdx.x; i < i1; i += kThreads) {
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += kAuxThreads) {
     if (mode == 0) v += a[i];
     else if (mode == 1) { const double r = a[i] - s; v += r * r; }
     else if (mode == 2) v = fmax(v, a[i] - b[i]);
@@ -405,7 +405,7 @@ __global__ void reduce_partial_kernel(int mode, const double* a, const double* b
   sh[threadIdx.x] = v;
   sh2[threadIdx.x] = v2;
   __syncthreads();
-  for (int k = kThreads / 2; k > 0; k >>= 1) {
+  for (int k = kAuxThreads / 2; k > 0; k >>= 1) {
     if (threadIdx.x < k) {
       if (mode == 2) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + k]);
       else sh[threadIdx.x] += sh[threadIdx.x + k];
@@ -455,7 +455,7 @@ __global__ void weights_kernel(const double* a, const double* b, int64_t n, cons
 namespace best {
 
 static int grid_for(int64_t n) {
-  int64_t g = (n + kThreads - 1) / kThreads;
+  int64_t g = (n + kAuxThreads - 1) / kAuxThreads;
   if (g < 1) g = 1;
   if (g > 8192) g = 8192;
   return (int)g;
@@ -465,28 +465,28 @@ hipError_t launch_init_positions(const Target& tg, const State& S, const Rng& rn
                                  const double* pt, double scale, const double* L0,
                                  hipStream_t s) {
   hipLaunchKernelGGL(init_positions_kernel, dim3(grid_for((int64_t)tg.d * S.N)),
-                     dim3(kThreads), 0, s, tg, S, rng, mode, pt, scale, L0);
+                     dim3(kAuxThreads), 0, s, tg, S, rng, mode, pt, scale, L0);
   return hipGetLastError();
 }
 
 hipError_t launch_rewhiten(const State& S, const Whiten& W, int d, hipStream_t s) {
-  hipLaunchKernelGGL(rewhiten_kernel, dim3(grid_for(S.N)), dim3(kThreads), 0, s, S, W, d);
+  hipLaunchKernelGGL(rewhiten_kernel, dim3(grid_for(S.N)), dim3(kAuxThreads), 0, s, S, W, d);
   return hipGetLastError();
 }
 
 hipError_t launch_da_update(const double* step_prob, int64_t N, double* da, hipStream_t s) {
-  hipLaunchKernelGGL(da_update_kernel, dim3(1), dim3(kThreads), 0, s, step_prob, N, da);
+  hipLaunchKernelGGL(da_update_kernel, dim3(1), dim3(kAuxThreads), 0, s, step_prob, N, da);
   return hipGetLastError();
 }
 
 hipError_t launch_stats(const State& S, int64_t* out_i, double* out_d, hipStream_t s) {
-  hipLaunchKernelGGL(stats_kernel, dim3(1), dim3(kThreads), 0, s, S, out_i, out_d);
+  hipLaunchKernelGGL(stats_kernel, dim3(1), dim3(kAuxThreads), 0, s, S, out_i, out_d);
   return hipGetLastError();
 }
 
 hipError_t launch_aies_record(const State& S, int d, float* rec, int64_t slot, int64_t pitch,
                               hipStream_t s) {
-  hipLaunchKernelGGL(aies_record_kernel, dim3(grid_for((int64_t)d * S.N)), dim3(kThreads), 0,
+  hipLaunchKernelGGL(aies_record_kernel, dim3(grid_for((int64_t)d * S.N)), dim3(kAuxThreads), 0,
                      s, S, d, rec, slot, pitch);
   return hipGetLastError();
 }
@@ -494,18 +494,18 @@ hipError_t launch_aies_record(const State& S, int d, float* rec, int64_t slot, i
 hipError_t launch_moments(const float* rec, const double* xs, int64_t T, int64_t N,
                           int64_t pitch, int d, const double* shift, double* part, int nblocks,
                           int update_mean, double* mu, double* L, double* info, hipStream_t s) {
-  hipLaunchKernelGGL(moments_partial_kernel, dim3(nblocks), dim3(kThreads), 0, s, rec, xs, T,
+  hipLaunchKernelGGL(moments_partial_kernel, dim3(nblocks), dim3(kAuxThreads), 0, s, rec, xs, T,
                      N, pitch, d, shift, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(moments_final_kernel, dim3(1), dim3(kThreads), 0, s, part, nblocks,
+  hipLaunchKernelGGL(moments_final_kernel, dim3(1), dim3(kAuxThreads), 0, s, part, nblocks,
                      T * N, d, shift, update_mean, mu, L, info);
   return hipGetLastError();
 }
 
 hipError_t launch_ess_chain_stats(const float* rec, int64_t T, int d, int64_t N, double* mean,
                                   double* ssq, hipStream_t s) {
-  hipLaunchKernelGGL(ess_chain_stats_kernel, dim3(grid_for((int64_t)d * N)), dim3(kThreads),
+  hipLaunchKernelGGL(ess_chain_stats_kernel, dim3(grid_for((int64_t)d * N)), dim3(kAuxThreads),
                      0, s, rec, T, d, N, mean, ssq);
   return hipGetLastError();
 }
@@ -517,13 +517,13 @@ hipError_t launch_ess_autocov(const float* rec, const double* mean, int64_t T, i
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(ess_autocov_kernel, dim3((unsigned)((N + 63) / 64), (unsigned)d),
-                     dim3(kThreads), lds, s, rec, mean, T, d, N, lag0, part);
+                     dim3(kAuxThreads), lds, s, rec, mean, T, d, N, lag0, part);
   return hipGetLastError();
 }
 
 hipError_t launch_adam(double* p, double* m, double* v, const double* g, int64_t n, double lr,
                        double b1, double b2, double eps, double c1, double c2, hipStream_t s) {
-  hipLaunchKernelGGL(adam_kernel, dim3(grid_for(n)), dim3(kThreads), 0, s, p, m, v, g, n, lr,
+  hipLaunchKernelGGL(adam_kernel, dim3(grid_for(n)), dim3(kAuxThreads), 0, s, p, m, v, g, n, lr,
                      b1, b2, eps, c1, c2);
   return hipGetLastError();
 }
@@ -532,20 +532,20 @@ hipError_t launch_dw(const float* dl, const float* h, const float* th, const flo
                      int64_t B, int d, int H, int nh, double* grad, const int64_t* offs,
                      const int64_t* w_offs_host, hipStream_t s) {
   for (int l = 2; l <= nh; ++l) {
-    hipLaunchKernelGGL(dw_gemm_kernel, dim3(H / 64, H / 64), dim3(kThreads), 0, s,
+    hipLaunchKernelGGL(dw_gemm_kernel, dim3(H / 64, H / 64), dim3(kAuxThreads), 0, s,
                        dl + (int64_t)(l - 1) * H * B, h + (int64_t)(l - 2) * H * B, B, B, H,
                        grad + w_offs_host[l - 2]);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   const int64_t n = (int64_t)H * d + (int64_t)nh * H + H + 1;
-  hipLaunchKernelGGL(dsmall_kernel, dim3(grid_for(n)), dim3(kThreads), 0, s, dl, h, th, up, B,
+  hipLaunchKernelGGL(dsmall_kernel, dim3(grid_for(n)), dim3(kAuxThreads), 0, s, dl, h, th, up, B,
                      B, d, H, nh, grad, offs);
   return hipGetLastError();
 }
 
 hipError_t launch_sum(const double* part, int n, double scale, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(kThreads), 0, s, part, n, scale, out);
+  hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(kAuxThreads), 0, s, part, n, scale, out);
   return hipGetLastError();
 }
 
@@ -553,7 +553,7 @@ hipError_t launch_sum(const double* part, int n, double scale, double* out, hipS
 static hipError_t reduce2(int mode, const double* a, const double* b, int64_t n, double shift,
                           double* part, double* out, hipStream_t s) {
   const int nb = 256;
-  hipLaunchKernelGGL(reduce_partial_kernel, dim3(nb), dim3(kThreads), 0, s, mode, a, b, n,
+  hipLaunchKernelGGL(reduce_partial_kernel, dim3(nb), dim3(kAuxThreads), 0, s, mode, a, b, n,
                      shift, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -573,7 +573,7 @@ hipError_t launch_standardise(const double* y, int64_t n, float* out, double* sc
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
   const double mu = sum[0] / (double)n;
   if ((e = reduce2(1, y, nullptr, n, mu, part, st + 2, s)) != hipSuccess) return e;
-  hipLaunchKernelGGL(standardise_kernel, dim3(grid_for(n)), dim3(kThreads), 0, s, y, n, st, out);
+  hipLaunchKernelGGL(standardise_kernel, dim3(grid_for(n)), dim3(kAuxThreads), 0, s, y, n, st, out);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = hipMemcpyAsync(stats_host, st, 32, hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
   return hipStreamSynchronize(s);
@@ -589,7 +589,7 @@ hipError_t launch_importance_weights(const double* lp, const double* le, int64_t
   if ((e = hipMemcpyAsync(mx, st, 16, hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
   if ((e = reduce2(3, lp, le, n, mx[0], part, st + 2, s)) != hipSuccess) return e;
-  hipLaunchKernelGGL(weights_kernel, dim3(grid_for(n)), dim3(kThreads), 0, s, lp, le, n, st, w);
+  hipLaunchKernelGGL(weights_kernel, dim3(grid_for(n)), dim3(kAuxThreads), 0, s, lp, le, n, st, w);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = hipMemcpyAsync(stats_host, st, 32, hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
   return hipStreamSynchronize(s);

@@ -6,18 +6,33 @@
 namespace best {
 
 // Flat FP64 parameters -> packed device copies used by the tile engine:
-//   wf: W_l in fragment order (rows = outputs), wb: W_l^T in fragment order,
-//   w1: [H][d], bias: [nh][H], wout: [H] followed by b_out.
+//   wf: W_l in fragment order (rows = outputs), wb: W_l^T in fragment order (l >= 2),
+//   w1f: W_1 in the input layer's fragment order (k = input component, zero padded),
+//   w1t: W_1^T in fragment order (rows = input components, zero padded to 16 rti),
+//   bias: [nh][H], wout: [H] followed by b_out.
+// Rounding of a parameter to a storage type: FP64 kept, FP32 round-to-nearest, the 16-bit
+// types via FP32.
+template <class T>
+__device__ __forceinline__ T to_store(double v) {
+  if constexpr (sizeof(T) == 8) return (T)v;
+  else return (T)(float)v;
+}
+
 template <class P>
 __global__ void pack_kernel(const double* flat, int d, int H, int nh, typename P::T* wf,
-                            typename P::T* wb, typename P::vec* w1, typename P::acc* bias,
-                            typename P::acc* wout) {
+                            typename P::T* wb, void* w1f_, typename P::T* w1t,
+                            typename P::acc* bias, typename P::acc* wout) {
   using T = typename P::T;
+  using IP = typename InPrec<P>::type;
+  typename IP::T* w1f = (typename IP::T*)w1f_;
   const int64_t HH = (int64_t)H * H;
   const int64_t nW = (int64_t)(nh - 1) * HH;
-  const int64_t total = nW + (int64_t)H * d + (int64_t)nh * H + H + 1;
+  const int64_t ks1 = (d + IP::KSTEP - 1) / IP::KSTEP, K1 = ks1 * IP::KSTEP;
+  const int64_t R1 = (d + 15) / 16 * 16;
+  const int64_t n1f = (int64_t)H * K1, n1t = R1 * H;
+  const int64_t total = nW + n1f + n1t + (int64_t)nh * H + H + 1;
   const int64_t KS = H / P::KSTEP;
-  const int64_t offW1 = 0, offb1 = (int64_t)H * d;
+  const int64_t offb1 = (int64_t)H * d;
   const int64_t blk = HH + H;  // one hidden block W_l + b_l (l >= 2)
   const int64_t offwo = offb1 + H + (int64_t)(nh - 1) * blk;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
@@ -25,21 +40,20 @@ __global__ void pack_kernel(const double* flat, int d, int H, int nh, typename P
     if (e < nW) {
       const int64_t l = e / HH, q = e % HH, j = q / H, k = q % H;  // layer l + 2
       const double v = flat[offb1 + H + l * blk + j * H + k];
-      wf[l * HH + frag_offset<P>(j, k, KS)] = (T)(float)v;
-      wb[l * HH + frag_offset<P>(k, j, KS)] = (T)(float)v;
-      if constexpr (sizeof(T) == 8) {
-        wf[l * HH + frag_offset<P>(j, k, KS)] = (T)v;
-        wb[l * HH + frag_offset<P>(k, j, KS)] = (T)v;
-      }
-    } else if (e < nW + (int64_t)H * d) {
-      const int64_t q = e - nW;
-      w1[q] = (typename P::vec)flat[offW1 + q];
-    } else if (e < nW + (int64_t)H * d + (int64_t)nh * H) {
-      const int64_t q = e - nW - (int64_t)H * d, l = q / H, j = q % H;
+      wf[l * HH + frag_offset<P>(j, k, KS)] = to_store<T>(v);
+      wb[l * HH + frag_offset<P>(k, j, KS)] = to_store<T>(v);
+    } else if (e < nW + n1f) {
+      const int64_t q = e - nW, j = q / K1, i = q % K1;
+      w1f[frag_offset<IP>(j, i, ks1)] = to_store<typename IP::T>(i < d ? flat[j * d + i] : 0.0);
+    } else if (e < nW + n1f + n1t) {
+      const int64_t q = e - nW - n1f, i = q / H, j = q % H;
+      w1t[frag_offset<P>(i, j, KS)] = to_store<T>(i < d ? flat[j * d + i] : 0.0);
+    } else if (e < nW + n1f + n1t + (int64_t)nh * H) {
+      const int64_t q = e - nW - n1f - n1t, l = q / H, j = q % H;
       const int64_t off = l == 0 ? offb1 : offb1 + H + (l - 1) * blk + HH;
       bias[q] = (typename P::acc)flat[off + j];
     } else {
-      const int64_t j = e - nW - (int64_t)H * d - (int64_t)nh * H;
+      const int64_t j = e - nW - n1f - n1t - (int64_t)nh * H;
       wout[j] = (typename P::acc)flat[offwo + j];  // j == H is b_out
     }
   }
@@ -63,11 +77,12 @@ __global__ __launch_bounds__(kThreads, 1) void train_tile_kernel(TrainArgs a) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
   using acc = typename P::acc;
   using vec = typename P::vec;
+  using IP = typename InPrec<P>::type;
   constexpr int M = 16 * MT;
-  const int tid = threadIdx.x, d = a.mp.d;
+  const int tid = threadIdx.x, d = a.mp.d, K1 = a.mp.ks1 * IP::KSTEP;
   acc* hsave = (acc*)a.hsave + (int64_t)blockIdx.x * a.hsave_stride;
   MlpSmem<P> s = mlp_smem<P, MT>(smem + a.lds.big, a.mp);
-  s.th = (vec*)(smem + a.lds.th);
+  s.thf = (typename IP::T*)(smem + a.lds.th);
   s.gth = (vec*)(smem + a.lds.gth);
   s.red = (acc*)(smem + a.lds.red);
   s.out = (acc*)(smem + a.lds.out);
@@ -76,14 +91,14 @@ __global__ __launch_bounds__(kThreads, 1) void train_tile_kernel(TrainArgs a) {
   for (int64_t tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
     const int64_t c0 = tile * M;
     const int mv = (int)((a.B - c0) < M ? (a.B - c0) : M);
-    for (int e = tid; e < M * d; e += kThreads) {
-      const int c = e / d, i = e % d;
+    for (int e = tid; e < M * K1; e += kThreads) {
+      const int c = e / K1, i = e % K1;
       float v = 0.f;
-      if (c < mv) {
+      if (c < mv && i < d) {
         v = a.t_in[(int64_t)a.perm[a.batch0 + c0 + c] * d + i];
         a.ex_th[(int64_t)i * a.B + c0 + c] = v;
       }
-      s.th[e] = (vec)v;
+      store_t<P>(s, a.mp, c, i, v);
     }
     __syncthreads();
     MlpExport ex{a.ex_h, a.ex_dl, a.B, c0, mv};

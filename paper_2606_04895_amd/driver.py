@@ -1,0 +1,113 @@
+"""Host-side drivers over the C ABI: the burn-in schedule of Sec. 4 and the learned-emulator
+pipeline.  Control flow only; every computation is a library call.
+
+Burn-in (Sec. 4, Sec. 4.3): the warm-up is split into windows ending at 1/4, 1/2 and all
+of the warm-up steps.  Inside a window the step size follows dual averaging towards the
+sampler's target acceptance; at its end the step size is set to the averaged iterate and
+the covariance and mean are re-estimated from the second half of the window (best_adapt),
+then dual averaging restarts from the new step size.  AIES uses no whitening and no step
+size, so its warm-up is a single plain run (Sec. 4: one long burn-in).
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+
+from . import (best_adapt, best_ess, best_init, best_logL_grad, best_set_mlp,
+               best_set_step_size, best_standardise, best_step, Trainer)
+
+TARGET_ACCEPT = {"mala": 0.57, "hmc": 0.8}
+EPS0 = {"mala": 0.5, "hmc": 0.3}
+
+
+def burn_in(ctx, sampler, warmup, d, n, n_leap=10, mh_scale=None, stretch_a=2.0):
+    import torch
+
+    kw = dict(n_leapfrog=n_leap, stretch_a=stretch_a,
+              mh_scale=mh_scale if mh_scale else 2.4 / np.sqrt(d))
+    t0 = time.perf_counter()
+    if sampler == "aies":
+        if warmup:
+            best_step(ctx, sampler, warmup, **kw)
+        return time.perf_counter() - t0
+    gradient = sampler in TARGET_ACCEPT
+    if gradient:
+        best_set_step_size(ctx, EPS0[sampler])
+    bounds = sorted(set([0, max(1, warmup // 4), max(1, warmup // 2), warmup]))
+    for a, b in zip(bounds[:-1], bounds[1:]):
+        w = b - a
+        rec = torch.empty((w, d, n), dtype=torch.float32, device="cuda")
+        if gradient:
+            best_step(ctx, sampler, w, record=rec, adapt_eps=True,
+                      target_accept=TARGET_ACCEPT[sampler], **kw)
+        else:
+            best_step(ctx, sampler, w, record=rec, **kw)
+        keep = rec[w // 2:] if w >= 4 else rec
+        best_adapt(ctx, samples=keep.contiguous(), update_mean=True, finalize_da=gradient,
+                   reset_da=gradient,
+                   target_accept=TARGET_ACCEPT.get(sampler, 0.0))
+        del rec
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def sample(ctx, sampler, steps, d, n, n_leap=10, mh_scale=None, stretch_a=2.0, ess=True):
+    """Timed production run with every step recorded; returns (stats, record, wall_s, ess)."""
+    import torch
+
+    kw = dict(n_leapfrog=n_leap, stretch_a=stretch_a,
+              mh_scale=mh_scale if mh_scale else 2.4 / np.sqrt(d))
+    rec = torch.empty((steps, d, n), dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = best_step(ctx, sampler, steps, record=rec, **kw)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    e = best_ess(ctx, rec) if ess else None
+    return st, rec, wall, e
+
+
+def train_emulator(prob, n_train, epochs, batch=1024, precision="fp32", seed=0,
+                   lr0=1e-3, lr1=1e-5, plain_precision="fp32"):
+    """Latin-hypercube design in the training box -> plain log L on the device ->
+    standardised targets -> minibatch Adam.  Returns a dict with the trained flat parameter
+    vector, the target scale (mean, std) and the per-epoch losses."""
+    import torch
+    from workloads import latin_hypercube, minibatch_permutations, xavier_mlp
+
+    rng = np.random.default_rng(seed)
+    d, w, nh = prob["d"], prob["width"], prob["n_hidden"]
+    t0 = time.perf_counter()
+    u = latin_hypercube(rng, n_train, d)
+    x = prob["train_lo"] + u * (prob["train_hi"] - prob["train_lo"])
+    plain = dict(prob, plain_mode=2)
+    ctx = best_init(plain, n_chains=16, precision=plain_precision, seed=seed)
+    xt = torch.tensor(x.T.copy(), device="cuda")
+    ll, _ = best_logL_grad(ctx, xt, want_grad=False)
+    y, mu, sig = best_standardise(ll)
+    th = torch.tensor((x - prob["in_center"]) * prob["in_invscale"], dtype=torch.float32,
+                      device="cuda")
+    t_data = time.perf_counter() - t0
+    tr = Trainer(d, w, nh, xavier_mlp(rng, d, w, nh), precision=precision)
+    perms = minibatch_permutations(rng, n_train, epochs)
+    nb = n_train // batch
+    losses = []
+    t1 = time.perf_counter()
+    for e in range(epochs):
+        pe = torch.tensor(perms[e], device="cuda")
+        losses.append(tr.epoch(th, y, pe, batch, lr0, lr1, e * nb, epochs * nb))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    out = dict(params=tr.params(), y_mu=mu, y_sigma=sig, losses=losses, data_s=t_data,
+               train_s=t_train, n_train=n_train, epochs=epochs)
+    tr.close()
+    ctx.close()
+    return out
+
+
+def emulator_problem(prob, trained):
+    """The sampling target built on the trained emulator: y_mu + y_sigma * MLP inside the
+    training box, the plain likelihood outside it."""
+    return dict(prob, plain_mode=1, mlp_params=trained["params"], mlp_coef=trained["y_sigma"],
+                offset=trained["y_mu"])

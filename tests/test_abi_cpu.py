@@ -62,7 +62,7 @@ def test_invalid_problem_rejected_before_device_work():
     lib = _abi.load()
     from paper_2606_04895_amd import _problem_struct
     prob = workloads.make_problem("c2")
-    bad = dict(prob, width=100)  # not a multiple of 64
+    bad = dict(prob, width=100)  # not a multiple of 128
     ps, keep = _problem_struct(bad)
     cfg = _abi.Config()
     cfg.n_chains = 16

@@ -20,7 +20,7 @@ def _ctx_at_mean(prob, n, prec="fp32", seed=3):
 
 
 def test_adapt_window_matches_oracle_moments_and_cholesky():
-    prob = small_problem(d=5, width=64, n_hidden=2)
+    prob = small_problem(d=5, width=128, n_hidden=2)
     n, T = 300, 40
     ctx = _ctx_at_mean(prob, n)
     rec = torch.empty((T, 5, n), dtype=torch.float32, device="cuda")
@@ -41,7 +41,7 @@ def test_adapt_window_matches_oracle_moments_and_cholesky():
 
 
 def test_adapt_rank_one_ensemble_takes_jitter_path():
-    prob = small_problem(d=4, width=64, n_hidden=2)
+    prob = small_problem(d=4, width=128, n_hidden=2)
     n = 64
     ctx = _ctx_at_mean(prob, n)
     t = np.linspace(-1, 1, n)
@@ -57,7 +57,7 @@ def test_adapt_rank_one_ensemble_takes_jitter_path():
 
 
 def test_adapt_collapsed_ensemble_reports_not_pd_and_keeps_whitening():
-    prob = small_problem(d=3, width=64, n_hidden=2)
+    prob = small_problem(d=3, width=128, n_hidden=2)
     ctx = _ctx_at_mean(prob, 32)
     mu0, L0 = B.best_get_whitening(ctx)
     B.best_set_state(ctx, np.tile(prob["gauss_mean"][:, None], (1, 32)))
@@ -83,7 +83,7 @@ def test_dual_averaging_reaches_target_acceptance(sampler, target):
 
 
 def test_ess_matches_oracle_on_ar1_chains():
-    prob = small_problem(d=3, width=64, n_hidden=2)
+    prob = small_problem(d=3, width=128, n_hidden=2)
     n, T = 256, 600
     ctx = _ctx_at_mean(prob, n)
     rng = np.random.default_rng(7)
@@ -97,7 +97,7 @@ def test_ess_matches_oracle_on_ar1_chains():
 
 def test_ess_long_lag_extension():
     """Strongly correlated chains need lags beyond the first 128-lag pass."""
-    prob = small_problem(d=3, width=64, n_hidden=2)
+    prob = small_problem(d=3, width=128, n_hidden=2)
     n, T = 64, 3000
     ctx = _ctx_at_mean(prob, n)
     rng = np.random.default_rng(8)
@@ -129,7 +129,7 @@ def test_training_gradient_matches_oracle(prec):
 
 
 def test_first_adam_step_matches_oracle():
-    d, w, nh, B_ = 6, 64, 2, 64
+    d, w, nh, B_ = 6, 128, 2, 64
     rng = np.random.default_rng(10)
     p = xavier_mlp(rng, d, w, nh)
     th = rng.uniform(-1, 1, size=(B_, d))

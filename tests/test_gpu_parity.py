@@ -51,7 +51,7 @@ def _check_eval(prob, prec, n, seed=0, ctx=None):
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16", "fp16"])
 @pytest.mark.parametrize("n", [1, 37, 333])
 def test_logL_grad_small_problem(prec, n):
-    prob = small_problem(d=5, width=64, n_hidden=3, twist=True)
+    prob = small_problem(d=5, width=128, n_hidden=3, twist=True)
     _check_eval(prob, prec, n)
 
 
@@ -84,7 +84,7 @@ def test_logL_grad_full_c2_batch_sampled():
 
 
 def test_box_and_nonfinite_handling():
-    prob = small_problem(d=4, width=64, n_hidden=2)
+    prob = small_problem(d=4, width=128, n_hidden=2)
     ctx = B.best_init(prob, n_chains=16, precision="fp32", seed=1)
     x = np.stack([prob["gauss_mean"], prob["upper"] + 1.0, prob["lower"]]).T.copy()
     lp, g = B.best_logL_grad(ctx, x)
@@ -168,7 +168,7 @@ def test_lockstep_small(prec, sampler, kw):
     if prec == "fp64" and sampler in ("mala", "hmc"):
         pytest.skip("FP64 gradient samplers are switched off in the library: an earlier build "
                     "of this path faulted on the GPU and the cause is not yet shown")
-    prob = small_problem(d=5, width=64, n_hidden=3, twist=True)
+    prob = small_problem(d=5, width=128, n_hidden=3, twist=True)
     band, tol = (1e-9, 1e-10) if prec == "fp64" else (1e-6, 1e-4)
     _lockstep(prob, prec, sampler, 262, steps=3, band=band, state_tol=tol, **kw)
 
@@ -190,7 +190,7 @@ def test_lockstep_c1_fp64_mh():
 # Determinism and error paths
 # ---------------------------------------------------------------------------------------
 def test_bitwise_determinism_across_runs_and_tile_widths():
-    prob = small_problem(d=5, width=64, n_hidden=3)
+    prob = small_problem(d=5, width=128, n_hidden=3)
     outs = []
     for cpb in (16, 32, 16):
         ctx = B.best_init(prob, n_chains=200, precision="fp32", seed=9, chains_per_block=cpb)
@@ -201,7 +201,7 @@ def test_bitwise_determinism_across_runs_and_tile_widths():
 
 
 def test_resume_from_checkpoint_is_bitwise():
-    prob = small_problem(d=5, width=64, n_hidden=2)
+    prob = small_problem(d=5, width=128, n_hidden=2)
     a = B.best_init(prob, n_chains=64, precision="fp32", seed=4)
     B.best_step(a, "hmc", 6, eps=0.2, n_leapfrog=4)
     xa = B.best_get_state(a)[0]
@@ -216,7 +216,7 @@ def test_resume_from_checkpoint_is_bitwise():
 
 
 def test_fp64_gradient_samplers_are_refused():
-    prob = small_problem(d=4, width=64, n_hidden=2)
+    prob = small_problem(d=4, width=128, n_hidden=2)
     ctx = B.best_init(prob, n_chains=32, precision="fp64", seed=1)
     for s in ("mala", "hmc"):
         with pytest.raises(B.BestError) as e:
@@ -225,7 +225,7 @@ def test_fp64_gradient_samplers_are_refused():
 
 
 def test_error_codes():
-    prob = small_problem(d=4, width=64, n_hidden=2)
+    prob = small_problem(d=4, width=128, n_hidden=2)
     ctx = B.best_init(prob, n_chains=33, precision="fp32", seed=1)
     with pytest.raises(B.BestError) as e:
         B.best_step(ctx, "aies", 1, stretch_a=2.0)
@@ -243,7 +243,7 @@ def test_error_codes():
 
 
 def test_nonfinite_weights_are_rejected_and_counted():
-    prob = small_problem(d=4, width=64, n_hidden=2)
+    prob = small_problem(d=4, width=128, n_hidden=2)
     p = prob["mlp_params"].copy()
     p[3] = np.nan
     ctx = B.best_init(prob, n_chains=32, precision="fp32", seed=1)
