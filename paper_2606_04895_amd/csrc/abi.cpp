@@ -135,12 +135,6 @@ MlpParams make_mlp_params(int prec, int d, int H, int nh, int lds_h, void* wf, v
   return mp;
 }
 
-// Packed hidden weights (forward and transposed copies) in the GEMM type.
-int64_t weight_bytes(int prec, int H, int nh) {
-  return 2LL * (nh - 1) * H * H * tsize(prec);
-}
-constexpr int64_t kL2Budget = 3LL << 20;  // of the 4 MiB L2 per XCD, leave room for state
-
 int64_t mlp_nparams_impl(int64_t d, int64_t w, int64_t nh) {
   return w * d + w + (nh - 1) * (w * w + w) + w + 1;
 }
@@ -323,10 +317,12 @@ static int validate_problem(best_ctx* h, const best_problem* p, const best_confi
   return BEST_OK;
 }
 
-// Chain-tile width and activation storage.  Every tile streams all packed weights once per
-// evaluation.  If they fit in L2 the streaming is L2->CU bound, so all CUs should get a tile
-// (tiles >= CUs); otherwise the traffic beyond L2 scales with the number of tiles and the
-// widest tile that fits LDS is preferred.  Activations stay in LDS when there is room.
+// Chain-tile width and activation storage.  Every tile streams all packed weights through
+// its CU once per evaluation, and a CU's weight stream (L2 hits, about 30 B per clock
+// measured on MI355X) is the dominant cost at small tiles; wider tiles amortise it over
+// more chains but leave CUs idle once there are fewer tiles than CUs.  So the widest tile
+// that still gives every CU a tile is taken (the narrowest if there are too few chains),
+// and the activations stay in LDS when there is room.
 static int choose_mt(best_ctx* h, const best_config* c) {
   auto fits = [&](int mt, int lh) {
     return layout_for(h->prec, mt, h->H, h->d, h->nh, lh).total <= kLdsMax;
@@ -336,12 +332,10 @@ static int choose_mt(best_ctx* h, const best_config* c) {
     mt = c->chains_per_block / 16;
     if (!fits(mt, 0)) return fail(h, BEST_EINVAL, "chains_per_block needs more LDS than 160 KiB");
   } else {
-    const bool l2_resident = weight_bytes(h->prec, h->H, h->nh) <= kL2Budget;
-    for (int m = mt_max(h->prec); m >= 1; m /= 2) {
-      if (!fits(m, 0)) continue;
+    for (int m = 1; m <= mt_max(h->prec); m *= 2) {
+      if (!fits(m, 0)) break;
+      if (mt && (h->N + 16 * m - 1) / (16 * m) < h->n_cu) break;
       mt = m;
-      if (!l2_resident) break;
-      if ((h->N + 16 * m - 1) / (16 * m) >= h->n_cu) break;
     }
     if (!mt) return fail(h, BEST_EINVAL, "MLP width too large for the LDS budget");
   }
@@ -595,6 +589,7 @@ int best_step(best_ctx* h, int32_t sampler, int64_t n_steps, const best_step_par
   HIPCHK(h, hipEventRecord(h->ev0, h->stream));
   KArgs a = base_args(h);
   a.sampler = sampler;
+  a.adapt = p->adapt_eps ? 1 : 0;
   a.mh_scale = p->mh_scale;
   a.stretch_a = p->stretch_a;
   a.n_leap = p->n_leapfrog;

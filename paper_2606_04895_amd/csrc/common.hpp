@@ -12,8 +12,13 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 namespace best {
 
-constexpr int kThreads = 512;  // 8 wave64 per tile workgroup, two per SIMD of a CU
-constexpr int kWaves = 8;
+// Waves per tile workgroup (BEST_WAVES = 4: one per SIMD with the whole register file;
+// 8: two per SIMD with half of it each).
+#ifndef BEST_WAVES
+#define BEST_WAVES 4
+#endif
+constexpr int kWaves = BEST_WAVES;
+constexpr int kThreads = 64 * kWaves;
 constexpr int kAuxThreads = 256;  // block size of the small reduction kernels
 constexpr int kMaxD = 32;
 
@@ -36,6 +41,7 @@ struct Prec<__bf16> {
   using frag = bf16x8;
   using accv = f32x4;
   static constexpr int EPL = 8, KSTEP = 32;
+  static constexpr bool ROWS4 = true;  // D slots r = 0..3 hold rows 4g .. 4g + 3
   __device__ static constexpr int drow(int g, int r) { return 4 * g + r; }
   __device__ static accv mma(frag a, frag b, accv c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
@@ -50,6 +56,7 @@ struct Prec<_Float16> {
   using frag = f16x8;
   using accv = f32x4;
   static constexpr int EPL = 8, KSTEP = 32;
+  static constexpr bool ROWS4 = true;
   __device__ static constexpr int drow(int g, int r) { return 4 * g + r; }
   __device__ static accv mma(frag a, frag b, accv c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
@@ -64,6 +71,7 @@ struct Prec<float> {
   using frag = f32x4;
   using accv = f32x4;
   static constexpr int EPL = 4, KSTEP = 16;
+  static constexpr bool ROWS4 = true;
   __device__ static constexpr int drow(int g, int r) { return 4 * g + r; }
   __device__ static accv mma(frag a, frag b, accv c) {
     c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], b[0], c, 0, 0, 0);
@@ -82,6 +90,7 @@ struct Prec<double> {
   using frag = f64x2;
   using accv = f64x4;
   static constexpr int EPL = 2, KSTEP = 8;
+  static constexpr bool ROWS4 = false;
   // the FP64 16x16x4 MFMA returns rows g + 4 r in slot r of lane group g (strided)
   __device__ static constexpr int drow(int g, int r) { return g + 4 * r; }
   __device__ static accv mma(frag a, frag b, accv c) {

@@ -39,7 +39,7 @@ struct State {
 
 // Byte offsets into dynamic LDS (computed on the host by lds_layout()).
 struct LdsLayout {
-  int big, th, gth, red, out, up, mi, md, total;
+  int big, th, gth, red, outp, out, up, mi, md, total;
 };
 
 __host__ __device__ inline int align16(int v) { return (v + 15) & ~15; }
@@ -62,6 +62,8 @@ __host__ __device__ inline LdsLayout lds_layout(int M, int H, int d, int nh, int
   o = align16(o + M * d * vsize);
   L.red = o;
   o = align16(o + kWaves * M * (d > 1 ? d : 1) * asize);
+  L.outp = o;
+  o = align16(o + kWaves * M * asize);
   L.out = o;
   o = align16(o + M * asize);
   L.up = o;
@@ -82,6 +84,7 @@ struct KArgs {
   Rng rng;
   LdsLayout lds;
   int sampler;
+  int adapt;  // step-size adaptation launch (one step, step size read from the device)
   int64_t step0;
   int n_steps;
   double eps;
@@ -225,6 +228,7 @@ __device__ __forceinline__ void eval_tile(const KArgs& a, char* smem, typename P
   s.thf = (typename IP::T*)(smem + L.th);
   s.gth = (vec*)(smem + L.gth);
   s.red = (acc*)(smem + L.red);
+  s.outp = (acc*)(smem + L.outp);
   s.out = (acc*)(smem + L.out);
   s.up = nullptr;
   int* inbox = (int*)(smem + L.mi);
@@ -250,11 +254,13 @@ __device__ __forceinline__ void eval_tile(const KArgs& a, char* smem, typename P
     inbox[c] = ib;
     intrain[c] = tg.plain_mode == 2 ? 0 : it;
   }
-  __syncthreads();
 
+  // the input layer joins the barrier that publishes the inputs and flags
   if (tg.plain_mode != 2) {
-    mlp_forward<P, MT>(a.mp, s, hsave, nullptr, grad);
-    if (grad) mlp_backward<P, MT>(a.mp, s, hsave, nullptr, true, true);
+    mlp_forward<P, MT>(a.mp, s, hsave, nullptr, grad, true, grad);
+    if (grad) mlp_backward<P, MT>(a.mp, s, hsave, nullptr, true, true, true);
+  } else {
+    __syncthreads();
   }
 
   // FP64 assembly region (reuses the activation buffers)
@@ -613,13 +619,16 @@ __device__ __forceinline__ void aies_tile(const KArgs& a, char* smem, typename P
 // ---------------------------------------------------------------------------------------
 // Kernels
 // ---------------------------------------------------------------------------------------
-template <class P, int MT, int SAMPLER>
+// ADAPT marks the launches of the step-size adaptation windows (one step per launch, step
+// size from the dual-averaging state); production launches are separate instantiations so
+// that profiles keep the two apart.
+template <class P, int MT, int SAMPLER, bool ADAPT>
 __global__ __launch_bounds__(kThreads, 1) void step_kernel(KArgs a) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
   using acc = typename P::acc;
   constexpr int M = 16 * MT;
   acc* hsave = (acc*)a.hsave + (int64_t)blockIdx.x * a.hsave_stride;
-  const double eps = a.eps_ptr ? *a.eps_ptr : a.eps;
+  const double eps = (ADAPT || a.eps_ptr) ? *a.eps_ptr : a.eps;
   for (int64_t tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
     const int64_t c0 = a.chain0 + tile * M;
     const int64_t lim = SAMPLER == 3 ? a.chain0 + a.st.N / 2 : a.st.N;

@@ -85,6 +85,7 @@ __global__ __launch_bounds__(kThreads, 1) void train_tile_kernel(TrainArgs a) {
   s.thf = (typename IP::T*)(smem + a.lds.th);
   s.gth = (vec*)(smem + a.lds.gth);
   s.red = (acc*)(smem + a.lds.red);
+  s.outp = (acc*)(smem + a.lds.outp);
   s.out = (acc*)(smem + a.lds.out);
   s.up = (acc*)(smem + a.lds.up);
   double* r2 = (double*)(smem + a.lds.md);
@@ -100,9 +101,8 @@ __global__ __launch_bounds__(kThreads, 1) void train_tile_kernel(TrainArgs a) {
       }
       store_t<P>(s, a.mp, c, i, v);
     }
-    __syncthreads();
     MlpExport ex{a.ex_h, a.ex_dl, a.B, c0, mv};
-    mlp_forward<P, MT>(a.mp, s, hsave, &ex, false);
+    mlp_forward<P, MT>(a.mp, s, hsave, &ex, false, true, false);
     if (tid < M) {
       double r = 0;
       if (tid < mv) r = (double)s.out[tid] - (double)a.y[a.perm[a.batch0 + c0 + tid]];
@@ -117,7 +117,7 @@ __global__ __launch_bounds__(kThreads, 1) void train_tile_kernel(TrainArgs a) {
       for (int c = 0; c < M; ++c) t += r2[c];
       a.loss_part[tile] = t;
     }
-    mlp_backward<P, MT>(a.mp, s, hsave, &ex, false, false);
+    mlp_backward<P, MT>(a.mp, s, hsave, &ex, false, false, false);
   }
 }
 
