@@ -38,6 +38,41 @@ def gemm_flops_per_eval(H, nh):
     return 2 * 2 * (nh - 1) * H * H
 
 
+KERNEL_SOURCES = os.path.join(ROOT, "paper_2606_04895_amd", "csrc")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_step_kernel_bf16_hmc_c2.txt")
+
+
+def kernel_source_hash():
+    """sha256 over the HIP/C++ sources of the library (names and contents, sorted)."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(KERNEL_SOURCES)):
+        path = os.path.join(KERNEL_SOURCES, name)
+        if os.path.isfile(path):
+            h.update(name.encode())
+            with open(path, "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(steps, chains, n_leap):
+    """HBM bytes per production launch of the dominant kernel, from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE, each scaled by the factor a plain device copy of
+    known size gives).  None if the summary is missing, was taken for another launch shape,
+    or the kernel sources have changed since."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            kv = dict(ln.split("=", 1) for ln in f.read().splitlines() if "=" in ln and not ln.startswith("#"))
+        kv = {k.strip(): v.strip() for k, v in kv.items()}
+        if kv.get("source_sha256") != kernel_source_hash():
+            return None
+        if (int(kv["steps"]), int(kv["chains"]), int(kv["n_leapfrog"])) != (steps, chains, n_leap):
+            return None
+        return float(kv["hbm_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def run_chain(B, torch, prob, prec, sampler, n, warmup, steps, seed, n_leap):
     from paper_2606_04895_amd import driver
 
@@ -95,8 +130,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--seed", type=int, default=0xBE570002)
-    ap.add_argument("--calib-copy-mib", type=int, default=0,
-                    help="run a plain device copy of this many MiB first (counter calibration)")
+    ap.add_argument("--calib-copy-mib", type=int, default=256,
+                    help="plain device copy of this many MiB at the start (the reference "
+                         "launch for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the sampler's chains "
@@ -142,9 +178,12 @@ def main():
     dom = "hmc" if "hmc" in samplers else samplers[0]
     r = results[head][dom]
     achieved = r["evals"] * fpe / (r["kernel_ms"] * 1e-3)
-    roof = dict(bound="mfma", kernel=f"step_kernel<{head}> ({dom})", achieved=achieved / 1e12,
-                peak=PEAK[head] / 1e12, unit="TFLOP/s", frac=achieved / PEAK[head],
-                traffic=None, flops_per_eval=fpe, evals_per_launch=r["evals"])
+    traffic = measured_traffic(args.steps, args.chains, args.n_leapfrog) \
+        if (head, dom, args.config) == ("bf16", "hmc", "c2") else None
+    roof = dict(bound="mfma", kernel=f"step_kernel<{head}, production> ({dom})",
+                achieved=achieved / 1e12, peak=PEAK[head] / 1e12, unit="TFLOP/s",
+                frac=achieved / PEAK[head], traffic=traffic, flops_per_eval=fpe,
+                evals_per_launch=r["evals"], launch_ms=r["kernel_ms"])
     line = dict(
         metric="min-ESS/s and emulator logL+grad evals/s at 4096 chains, bf16-MFMA vs fp32",
         value=value, unit="emulator logL+grad evals/s", n_gpus=1, steps=args.steps,
