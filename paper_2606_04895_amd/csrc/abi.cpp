@@ -108,7 +108,7 @@ int grad_rtiles(int d) { return (d + 15) / 16; }
 
 LdsLayout layout_for(int prec, int MT, int H, int d, int nh, int lds_h) {
   return lds_layout(16 * MT, H, d, nh, lds_h, tsize(prec), vasize(prec), vasize(prec),
-                    in_ksteps(prec, d) * in_kstep(prec), in_size(prec));
+                    in_ksteps(prec, d) * in_kstep(prec), in_size(prec), tile_waves(tsize(prec)));
 }
 
 // Packed input-layer weights: W_1 for the input GEMM and W_1^T for the input gradient.

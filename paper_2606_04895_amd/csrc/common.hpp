@@ -12,8 +12,11 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 namespace best {
 
-// Waves per tile workgroup (BEST_WAVES = 4: one per SIMD with the whole register file;
-// 8: two per SIMD with half of it each).
+// Waves per tile workgroup, by GEMM element size: 8 (two per SIMD) for the 16-bit types,
+// whose L2 weight stream needs the extra waves in flight, 4 (one per SIMD, the whole
+// register file each) for FP32 and FP64.  Each precision's translation unit sets
+// BEST_WAVES from this rule; the host sizes LDS with the same rule.
+constexpr int tile_waves(int elem_bytes) { return elem_bytes == 2 ? 8 : 4; }
 #ifndef BEST_WAVES
 #define BEST_WAVES 4
 #endif

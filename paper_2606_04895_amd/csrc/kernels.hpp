@@ -47,13 +47,13 @@ __host__ __device__ inline int align16(int v) { return (v + 15) & ~15; }
 // Union region: {activation slots or ping-pong buffers + delta buffers} during the MLP,
 // {R, PR, plain results, plain scratch} during the FP64 assembly.
 // The input buffer holds M x k1 values of isize bytes (d padded to the input layer's
-// k-step).
+// k-step); waves is the tile workgroup's wave count (per-wave partial sums).
 __host__ __device__ inline LdsLayout lds_layout(int M, int H, int d, int nh, int lds_h,
                                                int tsize, int vsize, int asize, int k1,
-                                               int isize) {
+                                               int isize, int waves) {
   LdsLayout L;
   const int mlp_bytes = (lds_h ? nh + 2 : 2) * M * H * tsize;
-  const int asm_bytes = 8 * (2 * d * M + M + M * d + kMaxD + 3 * kMaxTerms + kWaves * 32);
+  const int asm_bytes = 8 * (2 * d * M + M + M * d + kMaxD + 3 * kMaxTerms + waves * 32);
   L.big = 0;
   int o = align16(mlp_bytes > asm_bytes ? mlp_bytes : asm_bytes);
   L.th = o;
@@ -61,9 +61,9 @@ __host__ __device__ inline LdsLayout lds_layout(int M, int H, int d, int nh, int
   L.gth = o;
   o = align16(o + M * d * vsize);
   L.red = o;
-  o = align16(o + kWaves * M * (d > 1 ? d : 1) * asize);
+  o = align16(o + waves * M * (d > 1 ? d : 1) * asize);
   L.outp = o;
-  o = align16(o + kWaves * M * asize);
+  o = align16(o + waves * M * asize);
   L.out = o;
   o = align16(o + M * asize);
   L.up = o;
@@ -117,7 +117,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 __device__ __forceinline__ void plain_chain(const Target& tg, const double* __restrict__ X, int64_t pitch,
                             int64_t ch, bool grad, double* scratch, double* outv, double* outg) {
-  const int tid = threadIdx.x, d = tg.d, nt = tg.n_terms;
+  const int tid = local_tid(), d = tg.d, nt = tg.n_terms;
   double* tpl = scratch;                  // [kMaxD]
   double* A = tpl + kMaxD;                // [kMaxTerms]
   double* gam = A + kMaxTerms;            // [kMaxTerms]
@@ -222,7 +222,7 @@ __device__ __forceinline__ void eval_tile(const KArgs& a, char* smem, typename P
   using IP = typename InPrec<P>::type;
   constexpr int M = 16 * MT;
   const Target& tg = a.tg;
-  const int tid = threadIdx.x, d = tg.d;
+  const int tid = local_tid(), d = tg.d;
   const LdsLayout& L = a.lds;
   MlpSmem<P> s = mlp_smem<P, MT>(smem + L.big, a.mp);
   s.thf = (typename IP::T*)(smem + L.th);
@@ -336,7 +336,7 @@ __device__ __forceinline__ void eval_tile(const KArgs& a, char* smem, typename P
 __device__ __forceinline__ void tile_affine(const double* __restrict__ mu, const double* __restrict__ Lw,
                                    int d, int M, int mv, const double* __restrict__ Z,
                                    double* __restrict__ Xo, int64_t Np, int64_t c0) {
-  for (int e = threadIdx.x; e < d * M; e += kThreads) {
+  for (int e = local_tid(); e < d * M; e += kThreads) {
     const int i = e / M, c = e % M;
     if (c >= mv) continue;
     double v = 0;
@@ -353,7 +353,7 @@ __device__ __forceinline__ void tile_whiten(const double* __restrict__ mu,
                                             const double* __restrict__ Lw, int d, int mv,
                                             const double* __restrict__ X, double* __restrict__ Z,
                                             int64_t Np, int64_t c0) {
-  const int c = threadIdx.x;
+  const int c = local_tid();
   if (c < mv) {
     for (int i = 0; i < d; ++i) {
       double r = X[i * Np + c0 + c] - mu[i];
@@ -396,7 +396,7 @@ __device__ __forceinline__ void record_tile(const KArgs& a, int s, int d, int M,
   const int64_t slot = sc / a.thin - 1;
   if (slot >= a.rec_cap) return;
   const State& S = a.st;
-  for (int e = threadIdx.x; e < d * M; e += kThreads) {
+  for (int e = local_tid(); e < d * M; e += kThreads) {
     const int i = e / M, c = e % M;
     if (c >= mv) continue;
     a.record[(slot * d + i) * a.rec_pitch + c0 + c] = (float)S.x[i * S.Np + c0 + c];
@@ -406,7 +406,7 @@ __device__ __forceinline__ void record_tile(const KArgs& a, int s, int d, int M,
 // Copy proposal -> state for accepted chains (flag in LDS).
 __device__ __forceinline__ void commit_tile(const State& S, const int* flag, int d, int M, int mv,
                                    int64_t c0, bool with_z, bool with_g) {
-  for (int e = threadIdx.x; e < d * M; e += kThreads) {
+  for (int e = local_tid(); e < d * M; e += kThreads) {
     const int i = e / M, c = e % M;
     if (c >= mv || !flag[c]) continue;
     const int64_t o = i * S.Np + c0 + c;
@@ -424,7 +424,7 @@ __device__ __forceinline__ void mh_tile(const KArgs& a, char* smem, typename P::
                         uint64_t t) {
   constexpr int M = 16 * MT;
   const State& S = a.st;
-  const int d = a.tg.d, tid = threadIdx.x;
+  const int d = a.tg.d, tid = local_tid();
   const int64_t Np = S.Np;
   int* inbox = (int*)(smem + a.lds.mi);
   int* flag = inbox + 2 * M;
@@ -457,7 +457,7 @@ __device__ __forceinline__ void mala_tile(const KArgs& a, char* smem, typename P
                           int mv, uint64_t t, double eps) {
   constexpr int M = 16 * MT;
   const State& S = a.st;
-  const int d = a.tg.d, tid = threadIdx.x;
+  const int d = a.tg.d, tid = local_tid();
   const int64_t Np = S.Np;
   const double* Lw = a.wh.L;
   int* inbox = (int*)(smem + a.lds.mi);
@@ -508,7 +508,7 @@ __device__ __forceinline__ void hmc_tile(const KArgs& a, char* smem, typename P:
                          int mv, uint64_t t, double eps) {
   constexpr int M = 16 * MT;
   const State& S = a.st;
-  const int d = a.tg.d, tid = threadIdx.x;
+  const int d = a.tg.d, tid = local_tid();
   const int64_t Np = S.Np;
   const double* Lw = a.wh.L;
   int* inbox = (int*)(smem + a.lds.mi);
@@ -578,7 +578,7 @@ __device__ __forceinline__ void aies_tile(const KArgs& a, char* smem, typename P
                           int mv, uint64_t t) {
   constexpr int M = 16 * MT;
   const State& S = a.st;
-  const int d = a.tg.d, tid = threadIdx.x;
+  const int d = a.tg.d, tid = local_tid();
   const int64_t Np = S.Np, half = S.N / 2;
   const int h = a.aies_half;
   const int64_t other = (1 - h) * half;

@@ -29,6 +29,12 @@
 namespace best {
 
 constexpr int kPrefetch = 4;  // k-steps of weight fragments in flight per wave
+// Row tiles per register group: 4 with a whole register file per wave, 2 when two waves
+// share a SIMD.
+#ifndef BEST_RG_MAX
+#define BEST_RG_MAX (kWaves > 4 ? 2 : 4)
+#endif
+constexpr int kRgMax = BEST_RG_MAX;
 // Per-row-tile epilogue operands loaded before the k-loop: bias and output weights (8) in
 // the forward pass, the saved activations of the MT chain tiles (4 MT) in the backward.
 template <int MT>
@@ -83,6 +89,15 @@ struct MlpSmem {
   typename P::acc* up;               // [M] upstream gradient, NULL means 1
 };
 
+// threadIdx.x behind an empty asm: per-lane addresses derived from it are recomputed where
+// they are used instead of being hoisted out of the sampler loops, where they would stay
+// live across the whole kernel (and spill).
+__device__ __forceinline__ int local_tid() {
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
 template <class P>
 __device__ __forceinline__ int lds_off(int k, int c, int KS) {
   return (int)frag_offset<P>(c, k, KS);  // B fragments: column = chain, k = neuron
@@ -115,7 +130,7 @@ __device__ __forceinline__ void gemm_pass_rg(int n_layers, int KS, int rtw0, int
   using accv = typename P::accv;
   using acc = typename P::acc;
   constexpr int D = kPrefetch;
-  const int lane = threadIdx.x & 63;
+  const int lane = local_tid() & 63;
   const int ng = RTW / RG;
   frag a[D][RG];
   auto prologue = [&](const T* A, int rt0) {
@@ -141,26 +156,37 @@ __device__ __forceinline__ void gemm_pass_rg(int n_layers, int KS, int rtw0, int
       for (int rr = 0; rr < RG; ++rr)
 #pragma unroll
         for (int ct = 0; ct < MT; ++ct) c[rr][ct] = accv{};
-      auto step = [&](int ks, int p) {
-        frag b[MT];
+      // B fragments are double-buffered: the LDS read of k-step ks + 1 is issued before the
+      // MFMAs of k-step ks
+      frag b[MT];
 #pragma unroll
-        for (int ct = 0; ct < MT; ++ct) b[ct] = Bf[(ct * KS + ks) * 64];
+      for (int ct = 0; ct < MT; ++ct) b[ct] = Bf[ct * KS * 64];
+      auto step = [&](int ks, int p, bool next) {
+        frag bn[MT];
+        if (next) {
+#pragma unroll
+          for (int ct = 0; ct < MT; ++ct) bn[ct] = Bf[(ct * KS + ks + 1) * 64];
+        }
 #pragma unroll
         for (int rr = 0; rr < RG; ++rr)
 #pragma unroll
           for (int ct = 0; ct < MT; ++ct) c[rr][ct] = P::mma(a[p][rr], b[ct], c[rr][ct]);
+        if (next) {
+#pragma unroll
+          for (int ct = 0; ct < MT; ++ct) b[ct] = bn[ct];
+        }
       };
       int k0 = 0;
       for (; k0 < KS - D; k0 += D) {
 #pragma unroll
         for (int p = 0; p < D; ++p) {
-          step(k0 + p, p);
+          step(k0 + p, p, true);
 #pragma unroll
           for (int rr = 0; rr < RG; ++rr) a[p][rr] = Af[((int64_t)rr * KS + k0 + p + D) * 64];
         }
       }
 #pragma unroll
-      for (int p = 0; p < D; ++p) step(k0 + p, p);
+      for (int p = 0; p < D; ++p) step(k0 + p, p, p + 1 < D);
       if (gi + 1 < ng) prologue(A, rt0 + RG);
       else if (li + 1 < n_layers) prologue(Aof(li + 1), rtw0);
 #pragma unroll
@@ -175,7 +201,8 @@ template <class P, int MT, class AOf, class BOf, class Pre, class Epi>
 __device__ __forceinline__ void gemm_pass(int n_layers, int KS, int rtw0, int RTW, AOf& Aof,
                                           BOf& Bof, Pre& pre, Epi& epi) {
   if (n_layers <= 0) return;
-  if (RTW % 4 == 0) gemm_pass_rg<P, 4, MT>(n_layers, KS, rtw0, RTW, Aof, Bof, pre, epi);
+  if (kRgMax >= 4 && RTW % 4 == 0)
+    gemm_pass_rg<P, (kRgMax >= 4 ? 4 : 2), MT>(n_layers, KS, rtw0, RTW, Aof, Bof, pre, epi);
   else if (RTW % 2 == 0) gemm_pass_rg<P, 2, MT>(n_layers, KS, rtw0, RTW, Aof, Bof, pre, epi);
   else gemm_pass_rg<P, 1, MT>(n_layers, KS, rtw0, RTW, Aof, Bof, pre, epi);
 }
@@ -190,7 +217,7 @@ __device__ __forceinline__ void gemm_in(const typename IP::T* __restrict__ A, in
   using frag = typename IP::frag;
   using accv = typename IP::accv;
   using acc = typename IP::acc;
-  const int lane = threadIdx.x & 63;
+  const int lane = local_tid() & 63;
   const frag* __restrict__ Af = reinterpret_cast<const frag*>(A) + (int64_t)rt0 * KS * 64 + lane;
   const frag* __restrict__ Bf = reinterpret_cast<const frag*>(Bl) + lane;
   frag a[KS1][RG];
@@ -322,7 +349,7 @@ __device__ __forceinline__ void load_h(const MlpSmem<P>& s, const MlpParams& mp,
                                        typename P::acc* __restrict__ hsave, int l, int rt,
                                        int ct, typename P::acc h[4]) {
   using acc = typename P::acc;
-  const int lane = threadIdx.x & 63, g = lane >> 4, cl = lane & 15;
+  const int lane = local_tid() & 63, g = lane >> 4, cl = lane & 15;
   const int KS = mp.H / P::KSTEP, RT = mp.H / 16;
   if (mp.lds_h) {
     lds_load4<P>(layer_buf<P, MT>(s, mp, l), rt, g, ct * 16 + cl, KS, h);
@@ -359,7 +386,7 @@ __device__ __forceinline__ void mlp_forward(const MlpParams& mp, const MlpSmem<P
   using accv = typename P::accv;
   using IP = typename InPrec<P>::type;
   constexpr int M = 16 * MT;
-  const int tid = threadIdx.x, lane = tid & 63, g = lane >> 4, wv = tid >> 6, cl = lane & 15;
+  const int tid = local_tid(), lane = tid & 63, g = lane >> 4, wv = tid >> 6, cl = lane & 15;
   const int H = mp.H, nh = mp.nh;
   const int KS = H / P::KSTEP, RTW = H / (16 * kWaves), RT = H / 16;
   const acc* __restrict__ Bs = (const acc*)mp.bias;
@@ -472,7 +499,7 @@ __device__ __forceinline__ void mlp_backward(const MlpParams& mp, const MlpSmem<
   using accv = typename P::accv;
   using frag = typename P::frag;
   constexpr int M = 16 * MT;
-  const int tid = threadIdx.x, lane = tid & 63, g = lane >> 4, wv = tid >> 6, cl = lane & 15;
+  const int tid = local_tid(), lane = tid & 63, g = lane >> 4, wv = tid >> 6, cl = lane & 15;
   const int d = mp.d, H = mp.H, nh = mp.nh;
   const int KS = H / P::KSTEP, RTW = H / (16 * kWaves);
   const acc* __restrict__ Wo = (const acc*)mp.wout;

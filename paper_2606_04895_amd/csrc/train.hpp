@@ -79,7 +79,7 @@ __global__ __launch_bounds__(kThreads, 1) void train_tile_kernel(TrainArgs a) {
   using vec = typename P::vec;
   using IP = typename InPrec<P>::type;
   constexpr int M = 16 * MT;
-  const int tid = threadIdx.x, d = a.mp.d, K1 = a.mp.ks1 * IP::KSTEP;
+  const int tid = local_tid(), d = a.mp.d, K1 = a.mp.ks1 * IP::KSTEP;
   acc* hsave = (acc*)a.hsave + (int64_t)blockIdx.x * a.hsave_stride;
   MlpSmem<P> s = mlp_smem<P, MT>(smem + a.lds.big, a.mp);
   s.thf = (typename IP::T*)(smem + a.lds.th);
