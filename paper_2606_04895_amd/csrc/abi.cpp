@@ -106,9 +106,10 @@ int in_size(int prec) { return prec == BEST_FP64 ? 8 : 4; }
 int in_ksteps(int prec, int d) { return (d + in_kstep(prec) - 1) / in_kstep(prec); }
 int grad_rtiles(int d) { return (d + 15) / 16; }
 
-LdsLayout layout_for(int prec, int MT, int H, int d, int nh, int lds_h) {
+LdsLayout layout_for(int prec, int MT, int H, int d, int nh, int lds_h, int st_lds = 0) {
   return lds_layout(16 * MT, H, d, nh, lds_h, tsize(prec), vasize(prec), vasize(prec),
-                    in_ksteps(prec, d) * in_kstep(prec), in_size(prec), tile_waves(tsize(prec)));
+                    in_ksteps(prec, d) * in_kstep(prec), in_size(prec), tile_waves(tsize(prec)),
+                    st_lds);
 }
 
 // Packed input-layer weights: W_1 for the input GEMM and W_1^T for the input gradient.
@@ -145,7 +146,7 @@ struct best_ctx {
   std::string err;
   hipStream_t stream = nullptr;
   int n_cu = 256;
-  int d = 0, H = 0, nh = 0, prec = 0, MT = 1, lds_h = 0;
+  int d = 0, H = 0, nh = 0, prec = 0, MT = 1, lds_h = 0, st_lds = 0;
   int64_t N = 0, Np = 0;
   uint64_t seed = 0, step = 0;
   Arena mem;
@@ -317,12 +318,12 @@ static int validate_problem(best_ctx* h, const best_problem* p, const best_confi
   return BEST_OK;
 }
 
-// Chain-tile width and activation storage.  Every tile streams all packed weights through
-// its CU once per evaluation, and a CU's weight stream (L2 hits, about 30 B per clock
-// measured on MI355X) is the dominant cost at small tiles; wider tiles amortise it over
-// more chains but leave CUs idle once there are fewer tiles than CUs.  So the widest tile
-// that still gives every CU a tile is taken (the narrowest if there are too few chains),
-// and the activations stay in LDS when there is room.
+// Chain-tile width and LDS use.  Every tile streams all packed weights through its CU once
+// per evaluation, and a CU's weight stream (L2 hits, 40-55 B per clock measured on MI355X)
+// is the dominant cost at small tiles; wider tiles amortise it over more chains but leave
+// CUs idle once there are fewer tiles than CUs.  So the widest tile that still gives every
+// CU a tile is taken (the narrowest if there are too few chains); then the activations,
+// and then the sampler's per-step FP64 scratch, stay in LDS when there is room.
 static int choose_mt(best_ctx* h, const best_config* c) {
   auto fits = [&](int mt, int lh) {
     return layout_for(h->prec, mt, h->H, h->d, h->nh, lh).total <= kLdsMax;
@@ -341,6 +342,8 @@ static int choose_mt(best_ctx* h, const best_config* c) {
   }
   h->MT = mt;
   h->lds_h = fits(mt, 1) ? 1 : 0;
+  // the sampler's per-step FP64 scratch goes to LDS too when there is room
+  h->st_lds = layout_for(h->prec, mt, h->H, h->d, h->nh, h->lds_h, 1).total <= kLdsMax ? 1 : 0;
   return BEST_OK;
 }
 
@@ -448,7 +451,7 @@ int best_init(best_ctx** out, const best_problem* p, const best_config* c) {
   h->Np = (h->N + 63) / 64 * 64;
   h->seed = c->seed;
   if ((rc = choose_mt(h, c))) return bail(rc);
-  h->lds = layout_for(h->prec, h->MT, h->H, h->d, h->nh, h->lds_h);
+  h->lds = layout_for(h->prec, h->MT, h->H, h->d, h->nh, h->lds_h, h->st_lds);
   if ((rc = upload_problem(h, p))) return bail(rc);
   if ((rc = alloc_mlp(h))) return bail(rc);
   if (p->plain_mode != 2) {

@@ -39,7 +39,7 @@ struct State {
 
 // Byte offsets into dynamic LDS (computed on the host by lds_layout()).
 struct LdsLayout {
-  int big, th, gth, red, outp, out, up, mi, md, total;
+  int big, th, gth, red, outp, out, up, mi, md, st, cst, total;
 };
 
 __host__ __device__ inline int align16(int v) { return (v + 15) & ~15; }
@@ -48,9 +48,12 @@ __host__ __device__ inline int align16(int v) { return (v + 15) & ~15; }
 // {R, PR, plain results, plain scratch} during the FP64 assembly.
 // The input buffer holds M x k1 values of isize bytes (d padded to the input layer's
 // k-step); waves is the tile workgroup's wave count (per-wave partial sums).
+// With st_lds the per-step FP64 scratch of the tile (7 [d][M] arrays and log pi of the
+// proposals) and the launch's small constant arrays also live in LDS (st, cst >= 0), else
+// they stay in global memory (-1).
 __host__ __device__ inline LdsLayout lds_layout(int M, int H, int d, int nh, int lds_h,
                                                int tsize, int vsize, int asize, int k1,
-                                               int isize, int waves) {
+                                               int isize, int waves, int st_lds) {
   LdsLayout L;
   const int mlp_bytes = (lds_h ? nh + 2 : 2) * M * H * tsize;
   const int asm_bytes = 8 * (2 * d * M + M + M * d + kMaxD + 3 * kMaxTerms + waves * 32);
@@ -72,6 +75,13 @@ __host__ __device__ inline LdsLayout lds_layout(int M, int H, int d, int nh, int
   o = align16(o + 4 * M * 4);
   L.md = o;  // doubles: 8 per chain
   o = align16(o + 8 * M * 8);
+  L.st = L.cst = -1;
+  if (st_lds) {
+    L.st = o;
+    o = align16(o + (7 * d * M + M) * 8);
+    L.cst = o;  // launch constants: L, S^-1 (d x d), mu, gauss mean, box, input scaling
+    o = align16(o + (2 * d * d + 8 * d) * 8);
+  }
   L.total = o;
   return L;
 }
@@ -109,21 +119,31 @@ struct KArgs {
 // ---------------------------------------------------------------------------------------
 // Plain spectrum log-likelihood of one chain, computed by the whole workgroup.
 // ---------------------------------------------------------------------------------------
+// Element (i, c) of a tile's [d][M] FP64 array: the global SoA state (p = base + c0,
+// pitch = Np), a caller's array, or the tile's LDS scratch (pitch = M).
+struct TView {
+  double* p;
+  int64_t pitch;
+  __device__ __forceinline__ double& operator()(int i, int c) const {
+    return p[(int64_t)i * pitch + c];
+  }
+};
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
 
-__device__ __forceinline__ void plain_chain(const Target& tg, const double* __restrict__ X, int64_t pitch,
-                            int64_t ch, bool grad, double* scratch, double* outv, double* outg) {
+__device__ __forceinline__ void plain_chain(const Target& tg, const TView& X, int c, bool grad,
+                                            double* scratch, double* outv, double* outg) {
   const int tid = local_tid(), d = tg.d, nt = tg.n_terms;
   double* tpl = scratch;                  // [kMaxD]
   double* A = tpl + kMaxD;                // [kMaxTerms]
   double* gam = A + kMaxTerms;            // [kMaxTerms]
   double* tht = gam + kMaxTerms;          // [kMaxTerms]
   double* wred = tht + kMaxTerms;         // [kWaves][32]
-  if (tid < d) tpl[tid] = (X[tid * pitch + ch] - tg.pc[tid]) * tg.pis[tid];
+  if (tid < d) tpl[tid] = (X(tid, c) - tg.pc[tid]) * tg.pis[tid];
   __syncthreads();
   if (tid < nt) {
     double sa = 0, sg = 0, sp = 0;
@@ -214,9 +234,8 @@ __device__ __forceinline__ void plain_chain(const Target& tg, const double* __re
 // ---------------------------------------------------------------------------------------
 template <class P, int MT>
 __device__ __forceinline__ void eval_tile(const KArgs& a, char* smem, typename P::acc* hsave,
-                          const double* __restrict__ X, int64_t pitch, int64_t c0, int mv,
-                          double* __restrict__ LPo, double* __restrict__ GXo, int64_t opitch,
-                          bool grad, bool box) {
+                                          const TView& X, int mv, double* LPo, const TView& GXo,
+                                          bool grad, bool box) {
   using acc = typename P::acc;
   using vec = typename P::vec;
   using IP = typename InPrec<P>::type;
@@ -239,14 +258,14 @@ __device__ __forceinline__ void eval_tile(const KArgs& a, char* smem, typename P
   for (int e = tid; e < M * K1; e += kThreads) {
     const int c = e / K1, i = e % K1;
     double v = 0.0;
-    if (i < d && c < mv) v = (X[i * pitch + c0 + c] - tg.in_center[i]) * tg.in_invscale[i];
+    if (i < d && c < mv) v = (X(i, c) - tg.in_center[i]) * tg.in_invscale[i];
     store_t<P>(s, a.mp, c, i, v);
   }
   for (int c = tid; c < M; c += kThreads) {
     int ib = 1, it = 1;
     if (c < mv) {
       for (int i = 0; i < d; ++i) {
-        const double xv = X[i * pitch + c0 + c];
+        const double xv = X(i, c);
         ib &= (xv >= tg.lower[i]) & (xv <= tg.upper[i]);
         if (tg.plain_mode == 1) it &= (xv >= tg.train_lo[i]) & (xv <= tg.train_hi[i]);
       }
@@ -271,7 +290,7 @@ __device__ __forceinline__ void eval_tile(const KArgs& a, char* smem, typename P
   double* psc = pgr + M * d;   // plain scratch
   if (tg.plain_mode != 0) {
     for (int c = 0; c < mv; ++c) {
-      if (!intrain[c]) plain_chain(tg, X, pitch, c0 + c, grad, psc, pv + c, pgr + c * d);
+      if (!intrain[c]) plain_chain(tg, X, c, grad, psc, pv + c, pgr + c * d);
     }
   }
   if (tg.gauss_coef != 0.0) {
@@ -279,9 +298,9 @@ __device__ __forceinline__ void eval_tile(const KArgs& a, char* smem, typename P
       const int i = e / M, c = e % M;
       double y = 0;
       if (c < mv) {
-        y = X[i * pitch + c0 + c];
+        y = X(i, c);
         if (i == tg.tw_v) {
-          const double du = X[tg.tw_u * pitch + c0 + c] - tg.tw_center;
+          const double du = X(tg.tw_u, c) - tg.tw_center;
           y = y + tg.tw_beta * (du * du - tg.tw_kappa);
         }
       }
@@ -307,7 +326,7 @@ __device__ __forceinline__ void eval_tile(const KArgs& a, char* smem, typename P
     const bool use_mlp = tg.plain_mode == 0 || (tg.plain_mode == 1 && intrain[c]);
     lp += use_mlp ? tg.mlp_coef * (double)s.out[c] : pv[c];
     if (box && !inbox[c]) lp = -INFINITY;
-    LPo[c0 + c] = lp;
+    LPo[c] = lp;
   }
   if (grad) {
     for (int e = tid; e < d * M; e += kThreads) {
@@ -317,31 +336,70 @@ __device__ __forceinline__ void eval_tile(const KArgs& a, char* smem, typename P
       if (tg.gauss_coef != 0.0) {
         gi = -PR[e];
         if (i == tg.tw_u) {
-          const double du = X[tg.tw_u * pitch + c0 + c] - tg.tw_center;
+          const double du = X(tg.tw_u, c) - tg.tw_center;
           gi += -PR[tg.tw_v * M + c] * 2.0 * tg.tw_beta * du;
         }
         gi *= tg.gauss_coef;
       }
       const bool use_mlp = tg.plain_mode == 0 || (tg.plain_mode == 1 && intrain[c]);
       gi += use_mlp ? tg.mlp_coef * (double)s.gth[c * d + i] * tg.in_invscale[i] : pgr[c * d + i];
-      GXo[i * opitch + c0 + c] = gi;
+      GXo(i, c) = gi;
     }
   }
   __syncthreads();
 }
 
 // ---------------------------------------------------------------------------------------
+// Per-step FP64 scratch of a tile: whitened start z, proposal z' / x' / grad x', momentum q,
+// whitened gradients g_z (start) and g_z' (proposal), log pi of the proposal.  In LDS when
+// the layout has room (st >= 0), else in the global state arrays.
+// ---------------------------------------------------------------------------------------
+struct Scratch {
+  TView z, zp, xp, gxp, q, gz, gzp;
+  double* lpp;
+};
+
+template <int MT>
+__device__ __forceinline__ Scratch tile_scratch(const KArgs& a, char* smem, int64_t c0) {
+  constexpr int M = 16 * MT;
+  Scratch T;
+  if (a.lds.st >= 0) {
+    double* b = (double*)(smem + a.lds.st);
+    const int64_t n = (int64_t)a.tg.d * M;
+    T.z = TView{b, M};
+    T.zp = TView{b + n, M};
+    T.xp = TView{b + 2 * n, M};
+    T.gxp = TView{b + 3 * n, M};
+    T.q = TView{b + 4 * n, M};
+    T.gz = TView{b + 5 * n, M};
+    T.gzp = TView{b + 6 * n, M};
+    T.lpp = b + 7 * n;
+  } else {
+    const State& S = a.st;
+    T.z = TView{S.z + c0, S.Np};
+    T.zp = TView{S.zp + c0, S.Np};
+    T.xp = TView{S.xp + c0, S.Np};
+    T.gxp = TView{S.gxp + c0, S.Np};
+    T.q = TView{S.q + c0, S.Np};
+    T.gz = TView{S.gz + c0, S.Np};
+    T.gzp = TView{S.gzp + c0, S.Np};
+    T.lpp = S.lpp + c0;
+  }
+  return T;
+}
+
+// ---------------------------------------------------------------------------------------
 // Whitening helpers for a tile (thread per (i, c)); callers synchronise.
 // ---------------------------------------------------------------------------------------
-__device__ __forceinline__ void tile_affine(const double* __restrict__ mu, const double* __restrict__ Lw,
-                                   int d, int M, int mv, const double* __restrict__ Z,
-                                   double* __restrict__ Xo, int64_t Np, int64_t c0) {
+__device__ __forceinline__ void tile_affine(const double* __restrict__ mu,
+                                            const double* __restrict__ Lw, int d, int M, int mv,
+                                            const TView& Z, const TView& Xo) {
   for (int e = local_tid(); e < d * M; e += kThreads) {
     const int i = e / M, c = e % M;
     if (c >= mv) continue;
     double v = 0;
-    for (int j = 0; j <= i; ++j) v += Lw[i * d + j] * Z[j * Np + c0 + c];
-    Xo[i * Np + c0 + c] = mu[i] + v;
+    for (int j = 0; j <= i; ++j) v += Lw[i * d + j] * Z(j, c);
+    Xo(i, c) = mu[i] + v;
   }
 }
 
@@ -351,23 +409,23 @@ __device__ __forceinline__ void tile_affine(const double* __restrict__ mu, const
 // bit-for-bit.
 __device__ __forceinline__ void tile_whiten(const double* __restrict__ mu,
                                             const double* __restrict__ Lw, int d, int mv,
-                                            const double* __restrict__ X, double* __restrict__ Z,
-                                            int64_t Np, int64_t c0) {
+                                            const TView& X, const TView& Z) {
   const int c = local_tid();
   if (c < mv) {
     for (int i = 0; i < d; ++i) {
-      double r = X[i * Np + c0 + c] - mu[i];
-      for (int j = 0; j < i; ++j) r -= Lw[i * d + j] * Z[j * Np + c0 + c];
-      Z[i * Np + c0 + c] = r / Lw[i * d + i];
+      double r = X(i, c) - mu[i];
+      for (int j = 0; j < i; ++j) r -= Lw[i * d + j] * Z(j, c);
+      Z(i, c) = r / Lw[i * d + i];
     }
   }
   __syncthreads();
 }
 
+// (L^T g)_i = sum_{j >= i} L[j][i] g_j for chain c
 __device__ __forceinline__ double lt_dot(const double* __restrict__ Lw, int d, int i,
-                                const double* __restrict__ G, int64_t Np, int64_t ch) {
-  double v = 0;  // (L^T g)_i = sum_{j >= i} L[j][i] g_j
-  for (int j = i; j < d; ++j) v += Lw[j * d + i] * G[j * Np + ch];
+                                         const TView& G, int c) {
+  double v = 0;
+  for (int j = i; j < d; ++j) v += Lw[j * d + i] * G(j, c);
   return v;
 }
 
@@ -376,8 +434,8 @@ __device__ __forceinline__ double accept_prob(double la) {
 }
 
 // Accept bookkeeping for chain ch of the tile (called by one thread per chain).
-__device__ __forceinline__ bool decide(const KArgs& a, int64_t ch, uint64_t t, uint32_t sub, double la,
-                              double lpp, int inbox) {
+__device__ __forceinline__ bool decide(const KArgs& a, int64_t ch, uint64_t t, uint32_t sub,
+                                       double la, double lpp, int inbox) {
   const State& S = a.st;
   const double u = accept_uniform(a.rng, ch, t, sub);
   const bool acc = log(u) < la;
@@ -390,7 +448,8 @@ __device__ __forceinline__ bool decide(const KArgs& a, int64_t ch, uint64_t t, u
   return acc;
 }
 
-__device__ __forceinline__ void record_tile(const KArgs& a, int s, int d, int M, int mv, int64_t c0) {
+__device__ __forceinline__ void record_tile(const KArgs& a, int s, int d, int M, int mv,
+                                            int64_t c0) {
   const int64_t sc = a.rec_s0 + s + 1;
   if (!a.record || (sc % a.thin) != 0) return;
   const int64_t slot = sc / a.thin - 1;
@@ -403,16 +462,15 @@ __device__ __forceinline__ void record_tile(const KArgs& a, int s, int d, int M,
   }
 }
 
-// Copy proposal -> state for accepted chains (flag in LDS).
-__device__ __forceinline__ void commit_tile(const State& S, const int* flag, int d, int M, int mv,
-                                   int64_t c0, bool with_z, bool with_g) {
+// Copy the proposal into the chain state for accepted chains (flag in LDS).
+__device__ __forceinline__ void commit_tile(const State& S, const Scratch& T, const int* flag,
+                                            int d, int M, int mv, int64_t c0, bool with_g) {
   for (int e = local_tid(); e < d * M; e += kThreads) {
     const int i = e / M, c = e % M;
     if (c >= mv || !flag[c]) continue;
     const int64_t o = i * S.Np + c0 + c;
-    S.x[o] = S.xp[o];
-    if (with_z) S.z[o] = S.zp[o];
-    if (with_g) S.gx[o] = S.gxp[o];
+    S.x[o] = T.xp(i, c);
+    if (with_g) S.gx[o] = T.gxp(i, c);
   }
 }
 
@@ -420,147 +478,143 @@ __device__ __forceinline__ void commit_tile(const State& S, const int* flag, int
 // Transitions for one tile at global step t.
 // ---------------------------------------------------------------------------------------
 template <class P, int MT>
-__device__ __forceinline__ void mh_tile(const KArgs& a, char* smem, typename P::acc* hsave, int64_t c0, int mv,
-                        uint64_t t) {
+__device__ __forceinline__ void mh_tile(const KArgs& a, char* smem, typename P::acc* hsave,
+                                        int64_t c0, int mv, uint64_t t) {
   constexpr int M = 16 * MT;
   const State& S = a.st;
   const int d = a.tg.d, tid = local_tid();
-  const int64_t Np = S.Np;
+  const Scratch T = tile_scratch<MT>(a, smem, c0);
   int* inbox = (int*)(smem + a.lds.mi);
   int* flag = inbox + 2 * M;
-  tile_whiten(a.wh.mu, a.wh.L, d, mv, S.x, S.z, Np, c0);
+  tile_whiten(a.wh.mu, a.wh.L, d, mv, TView{S.x + c0, S.Np}, T.z);
   for (int e = tid; e < d * M; e += kThreads) {
     const int i = e / M, c = e % M;
     if (c >= mv) continue;
-    const int64_t ch = c0 + c, o = i * Np + ch;
-    S.zp[o] = S.z[o] + a.mh_scale * normal_dim(a.rng, ch, t, kStreamNormal, 0, i);
+    T.zp(i, c) = T.z(i, c) + a.mh_scale * normal_dim(a.rng, c0 + c, t, kStreamNormal, 0, i);
   }
   __syncthreads();
-  tile_affine(a.wh.mu, a.wh.L, d, M, mv, S.zp, S.xp, Np, c0);
+  tile_affine(a.wh.mu, a.wh.L, d, M, mv, T.zp, T.xp);
   __syncthreads();
-  eval_tile<P, MT>(a, smem, hsave, S.xp, Np, c0, mv, S.lpp, S.gxp, Np, false, true);
+  eval_tile<P, MT>(a, smem, hsave, T.xp, mv, T.lpp, T.gxp, false, true);
   if (tid < mv) {
     const int64_t ch = c0 + tid;
-    const double lpp = S.lpp[ch];
+    const double lpp = T.lpp[tid];
     const double la = lpp - S.lp[ch];
     const bool acc = decide(a, ch, t, 0, la, lpp, inbox[tid]);
     flag[tid] = acc;
     if (acc) S.lp[ch] = lpp;
   }
   __syncthreads();
-  commit_tile(S, flag, d, M, mv, c0, true, false);
+  commit_tile(S, T, flag, d, M, mv, c0, false);
   __syncthreads();
 }
 
 template <class P, int MT>
-__device__ __forceinline__ void mala_tile(const KArgs& a, char* smem, typename P::acc* hsave, int64_t c0,
-                          int mv, uint64_t t, double eps) {
+__device__ __forceinline__ void mala_tile(const KArgs& a, char* smem, typename P::acc* hsave,
+                                          int64_t c0, int mv, uint64_t t, double eps) {
   constexpr int M = 16 * MT;
   const State& S = a.st;
   const int d = a.tg.d, tid = local_tid();
-  const int64_t Np = S.Np;
   const double* Lw = a.wh.L;
+  const Scratch T = tile_scratch<MT>(a, smem, c0);
+  const TView GX{S.gx + c0, S.Np};
   int* inbox = (int*)(smem + a.lds.mi);
   int* flag = inbox + 2 * M;
   const double sq = sqrt(2.0 * eps);
-  tile_whiten(a.wh.mu, Lw, d, mv, S.x, S.z, Np, c0);
+  tile_whiten(a.wh.mu, Lw, d, mv, TView{S.x + c0, S.Np}, T.z);
   for (int e = tid; e < d * M; e += kThreads) {
     const int i = e / M, c = e % M;
     if (c >= mv) continue;
-    const int64_t ch = c0 + c, o = i * Np + ch;
-    const double gzi = lt_dot(Lw, d, i, S.gx, Np, ch);
-    S.gz[o] = gzi;
-    S.zp[o] = S.z[o] + eps * gzi + sq * normal_dim(a.rng, ch, t, kStreamNormal, 0, i);
+    const double gzi = lt_dot(Lw, d, i, GX, c);
+    T.gz(i, c) = gzi;
+    T.zp(i, c) = T.z(i, c) + eps * gzi + sq * normal_dim(a.rng, c0 + c, t, kStreamNormal, 0, i);
   }
   __syncthreads();
-  tile_affine(a.wh.mu, Lw, d, M, mv, S.zp, S.xp, Np, c0);
+  tile_affine(a.wh.mu, Lw, d, M, mv, T.zp, T.xp);
   __syncthreads();
-  eval_tile<P, MT>(a, smem, hsave, S.xp, Np, c0, mv, S.lpp, S.gxp, Np, true, true);
+  eval_tile<P, MT>(a, smem, hsave, T.xp, mv, T.lpp, T.gxp, true, true);
   for (int e = tid; e < d * M; e += kThreads) {
     const int i = e / M, c = e % M;
     if (c >= mv) continue;
-    S.gzp[i * Np + c0 + c] = lt_dot(Lw, d, i, S.gxp, Np, c0 + c);
+    T.gzp(i, c) = lt_dot(Lw, d, i, T.gxp, c);
   }
   __syncthreads();
   if (tid < mv) {
-    const int64_t ch = c0 + tid;
+    const int c = tid;
+    const int64_t ch = c0 + c;
     double fwd = 0, rev = 0;
     for (int i = 0; i < d; ++i) {
-      const int64_t o = i * Np + ch;
-      const double df = S.zp[o] - S.z[o] - eps * S.gz[o];
-      const double dr = S.z[o] - S.zp[o] - eps * S.gzp[o];
+      const double df = T.zp(i, c) - T.z(i, c) - eps * T.gz(i, c);
+      const double dr = T.z(i, c) - T.zp(i, c) - eps * T.gzp(i, c);
       fwd += df * df;
       rev += dr * dr;
     }
-    const double lpp = S.lpp[ch];
+    const double lpp = T.lpp[c];
     const double la = lpp - S.lp[ch] + (-rev / (4.0 * eps)) - (-fwd / (4.0 * eps));
-    const bool acc = decide(a, ch, t, 0, la, lpp, inbox[tid]);
-    flag[tid] = acc;
+    const bool acc = decide(a, ch, t, 0, la, lpp, inbox[c]);
+    flag[c] = acc;
     if (acc) S.lp[ch] = lpp;
   }
   __syncthreads();
-  commit_tile(S, flag, d, M, mv, c0, true, true);
+  commit_tile(S, T, flag, d, M, mv, c0, true);
   __syncthreads();
 }
 
 template <class P, int MT>
-__device__ __forceinline__ void hmc_tile(const KArgs& a, char* smem, typename P::acc* hsave, int64_t c0,
-                         int mv, uint64_t t, double eps) {
+__device__ __forceinline__ void hmc_tile(const KArgs& a, char* smem, typename P::acc* hsave,
+                                         int64_t c0, int mv, uint64_t t, double eps) {
   constexpr int M = 16 * MT;
   const State& S = a.st;
   const int d = a.tg.d, tid = local_tid();
-  const int64_t Np = S.Np;
   const double* Lw = a.wh.L;
+  const Scratch T = tile_scratch<MT>(a, smem, c0);
+  const TView GX{S.gx + c0, S.Np};
   int* inbox = (int*)(smem + a.lds.mi);
   int* flag = inbox + 2 * M;
   double* h0 = (double*)(smem + a.lds.md);
   const double he = 0.5 * eps;
-  tile_whiten(a.wh.mu, Lw, d, mv, S.x, S.z, Np, c0);
+  tile_whiten(a.wh.mu, Lw, d, mv, TView{S.x + c0, S.Np}, T.z);
   // momentum, copies of the start point, whitened start gradient
   for (int e = tid; e < d * M; e += kThreads) {
     const int i = e / M, c = e % M;
     if (c >= mv) continue;
-    const int64_t ch = c0 + c, o = i * Np + ch;
-    S.q[o] = normal_dim(a.rng, ch, t, kStreamNormal, 0, i);
-    S.zp[o] = S.z[o];
-    S.gzp[o] = lt_dot(Lw, d, i, S.gx, Np, ch);
+    T.q(i, c) = normal_dim(a.rng, c0 + c, t, kStreamNormal, 0, i);
+    T.zp(i, c) = T.z(i, c);
+    T.gzp(i, c) = lt_dot(Lw, d, i, GX, c);
   }
   __syncthreads();
   if (tid < mv) {
-    const int64_t ch = c0 + tid;
     double k = 0;
-    for (int i = 0; i < d; ++i) k += S.q[i * Np + ch] * S.q[i * Np + ch];
-    h0[tid] = -S.lp[ch] + 0.5 * k;
+    for (int i = 0; i < d; ++i) k += T.q(i, tid) * T.q(i, tid);
+    h0[tid] = -S.lp[c0 + tid] + 0.5 * k;
   }
   __syncthreads();
   for (int l = 0; l < a.n_leap; ++l) {
     for (int e = tid; e < d * M; e += kThreads) {
       const int i = e / M, c = e % M;
       if (c >= mv) continue;
-      const int64_t o = i * Np + c0 + c;
-      const double qh = S.q[o] + he * S.gzp[o];
-      S.q[o] = qh;
-      S.zp[o] = S.zp[o] + eps * qh;
+      const double qh = T.q(i, c) + he * T.gzp(i, c);
+      T.q(i, c) = qh;
+      T.zp(i, c) = T.zp(i, c) + eps * qh;
     }
     __syncthreads();
-    tile_affine(a.wh.mu, Lw, d, M, mv, S.zp, S.xp, Np, c0);
+    tile_affine(a.wh.mu, Lw, d, M, mv, T.zp, T.xp);
     __syncthreads();
-    eval_tile<P, MT>(a, smem, hsave, S.xp, Np, c0, mv, S.lpp, S.gxp, Np, true, false);
+    eval_tile<P, MT>(a, smem, hsave, T.xp, mv, T.lpp, T.gxp, true, false);
     for (int e = tid; e < d * M; e += kThreads) {
       const int i = e / M, c = e % M;
       if (c >= mv) continue;
-      const int64_t o = i * Np + c0 + c;
-      const double gzi = lt_dot(Lw, d, i, S.gxp, Np, c0 + c);
-      S.gzp[o] = gzi;
-      S.q[o] = S.q[o] + he * gzi;
+      const double gzi = lt_dot(Lw, d, i, T.gxp, c);
+      T.gzp(i, c) = gzi;
+      T.q(i, c) = T.q(i, c) + he * gzi;
     }
     __syncthreads();
   }
   if (tid < mv) {
     const int64_t ch = c0 + tid;
     double k = 0;
-    for (int i = 0; i < d; ++i) k += S.q[i * Np + ch] * S.q[i * Np + ch];
-    const double lp1 = inbox[tid] ? S.lpp[ch] : -INFINITY;
+    for (int i = 0; i < d; ++i) k += T.q(i, tid) * T.q(i, tid);
+    const double lp1 = inbox[tid] ? T.lpp[tid] : -INFINITY;
     const double h1 = -lp1 + 0.5 * k;
     const double la = h0[tid] - h1;
     const bool acc = decide(a, ch, t, 0, la, lp1, inbox[tid]);
@@ -568,20 +622,21 @@ __device__ __forceinline__ void hmc_tile(const KArgs& a, char* smem, typename P:
     if (acc) S.lp[ch] = lp1;
   }
   __syncthreads();
-  commit_tile(S, flag, d, M, mv, c0, true, true);
+  commit_tile(S, T, flag, d, M, mv, c0, true);
   __syncthreads();
 }
 
 // AIES: walkers of the active half [chain0, chain0 + half) against the other half.
 template <class P, int MT>
-__device__ __forceinline__ void aies_tile(const KArgs& a, char* smem, typename P::acc* hsave, int64_t c0,
-                          int mv, uint64_t t) {
+__device__ __forceinline__ void aies_tile(const KArgs& a, char* smem, typename P::acc* hsave,
+                                          int64_t c0, int mv, uint64_t t) {
   constexpr int M = 16 * MT;
   const State& S = a.st;
   const int d = a.tg.d, tid = local_tid();
   const int64_t Np = S.Np, half = S.N / 2;
   const int h = a.aies_half;
   const int64_t other = (1 - h) * half;
+  const Scratch T = tile_scratch<MT>(a, smem, c0);
   int* inbox = (int*)(smem + a.lds.mi);
   int* flag = inbox + 2 * M;
   double* zz = (double*)(smem + a.lds.md);
@@ -599,21 +654,54 @@ __device__ __forceinline__ void aies_tile(const KArgs& a, char* smem, typename P
     const double z = zr * zr / av;
     if (i == 0) zz[c] = z;
     const double xj = S.x[i * Np + j];
-    S.xp[i * Np + k] = xj + z * (S.x[i * Np + k] - xj);
+    T.xp(i, c) = xj + z * (S.x[i * Np + k] - xj);
   }
   __syncthreads();
-  eval_tile<P, MT>(a, smem, hsave, S.xp, Np, c0, mv, S.lpp, S.gxp, Np, false, true);
+  eval_tile<P, MT>(a, smem, hsave, T.xp, mv, T.lpp, T.gxp, false, true);
   if (tid < mv) {
     const int64_t k = c0 + tid;
-    const double lpp = S.lpp[k];
+    const double lpp = T.lpp[tid];
     const double la = (double)(d - 1) * log(zz[tid]) + lpp - S.lp[k];
     const bool acc = decide(a, k, t, (uint32_t)h, la, lpp, inbox[tid]);
     flag[tid] = acc;
     if (acc) S.lp[k] = lpp;
   }
   __syncthreads();
-  commit_tile(S, flag, d, M, mv, c0, false, false);
+  commit_tile(S, T, flag, d, M, mv, c0, false);
   __syncthreads();
+}
+
+// Copy the launch's small constant arrays (whitening, Gaussian part, box, input scaling)
+// into LDS and point the kernel's argument copy at them; they are read in every phase of
+// every step.
+__device__ __forceinline__ void stage_constants(KArgs& a, char* smem) {
+  if (a.lds.cst < 0) return;
+  const int d = a.tg.d, dd = d * d, tid = local_tid();
+  double* c = (double*)(smem + a.lds.cst);
+  auto copy = [&](const double* src, double* dst, int n) {
+    for (int e = tid; e < n; e += kThreads) dst[e] = src[e];
+  };
+  copy(a.wh.L, c, dd);
+  copy(a.tg.gprec, c + dd, dd);
+  copy(a.wh.mu, c + 2 * dd, d);
+  copy(a.tg.gmean, c + 2 * dd + d, d);
+  copy(a.tg.lower, c + 2 * dd + 2 * d, d);
+  copy(a.tg.upper, c + 2 * dd + 3 * d, d);
+  copy(a.tg.in_center, c + 2 * dd + 4 * d, d);
+  copy(a.tg.in_invscale, c + 2 * dd + 5 * d, d);
+  copy(a.tg.train_lo, c + 2 * dd + 6 * d, d);
+  copy(a.tg.train_hi, c + 2 * dd + 7 * d, d);
+  __syncthreads();
+  a.wh.L = c;
+  a.tg.gprec = c + dd;
+  a.wh.mu = c + 2 * dd;
+  a.tg.gmean = c + 2 * dd + d;
+  a.tg.lower = c + 2 * dd + 2 * d;
+  a.tg.upper = c + 2 * dd + 3 * d;
+  a.tg.in_center = c + 2 * dd + 4 * d;
+  a.tg.in_invscale = c + 2 * dd + 5 * d;
+  a.tg.train_lo = c + 2 * dd + 6 * d;
+  a.tg.train_hi = c + 2 * dd + 7 * d;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -629,6 +717,7 @@ __global__ __launch_bounds__(kThreads, 1) void step_kernel(KArgs a) {
   constexpr int M = 16 * MT;
   acc* hsave = (acc*)a.hsave + (int64_t)blockIdx.x * a.hsave_stride;
   const double eps = (ADAPT || a.eps_ptr) ? *a.eps_ptr : a.eps;
+  stage_constants(a, smem);
   for (int64_t tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
     const int64_t c0 = a.chain0 + tile * M;
     const int64_t lim = SAMPLER == 3 ? a.chain0 + a.st.N / 2 : a.st.N;
@@ -652,10 +741,12 @@ __global__ __launch_bounds__(kThreads, 1) void eval_kernel(KArgs a) {
   constexpr int M = 16 * MT;
   acc* hsave = (acc*)a.hsave + (int64_t)blockIdx.x * a.hsave_stride;
   const int64_t n = a.st.N;
+  stage_constants(a, smem);
   for (int64_t tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
     const int64_t c0 = tile * M;
     const int mv = (int)((n - c0) < M ? (n - c0) : M);
-    eval_tile<P, MT>(a, smem, hsave, a.ex_x, a.ex_pitch, c0, mv, a.ex_lp, a.ex_g, a.ex_pitch,
+    eval_tile<P, MT>(a, smem, hsave, TView{const_cast<double*>(a.ex_x) + c0, a.ex_pitch}, mv,
+                     a.ex_lp + c0, TView{a.ex_g ? a.ex_g + c0 : nullptr, a.ex_pitch},
                      a.ex_grad != 0, true);
   }
 }
