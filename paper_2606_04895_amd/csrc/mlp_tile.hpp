@@ -28,7 +28,10 @@
 
 namespace best {
 
-constexpr int kPrefetch = 4;  // k-steps of weight fragments in flight per wave
+#ifndef BEST_PREFETCH
+#define BEST_PREFETCH 4
+#endif
+constexpr int kPrefetch = BEST_PREFETCH;  // k-steps of weight fragments in flight per wave
 // Row tiles per register group: 4 with a whole register file per wave, 2 when two waves
 // share a SIMD.
 #ifndef BEST_RG_MAX

@@ -2,7 +2,7 @@
 pipeline.  Control flow only; every computation is a library call.
 
 Burn-in (Sec. 3.2, Sec. 4, Sec. 4.3): the warm-up is split into windows that double in
-length from a short first one, or that end at 1/4, 1/2 and all of the warm-up.
+length from a short first one (10 steps), or that end at 1/4, 1/2 and all of the warm-up.
 Inside a window the step size follows dual averaging towards the sampler's target
 acceptance; at its end the step size is set to the averaged iterate and the covariance and
 mean are re-estimated from the second half of the window (best_adapt), then dual averaging
@@ -24,7 +24,7 @@ TARGET_ACCEPT = {"mala": 0.57, "hmc": 0.8}
 EPS0 = {"mala": 0.5, "hmc": 0.3}
 
 
-def window_plan(warmup, schedule="doubling", first=25):
+def window_plan(warmup, schedule="doubling", first=10):
     """Adaptation windows as (length, re-estimate covariance) pairs.
     "doubling": windows of first, 2 first, 4 first, ... steps with a covariance update after
     each, the last of them absorbing the remainder, then a final step-size-only window of a
