@@ -63,8 +63,17 @@ __host__ __device__ inline LdsLayout lds_layout(int M, int H, int d, int nh, int
   o = align16(o + M * k1 * isize);
   L.gth = o;
   o = align16(o + M * d * vsize);
-  L.red = o;
-  o = align16(o + waves * M * (d > 1 ? d : 1) * asize);
+  // input-gradient partial sums: inside the delta buffer that does not hold delta_1 when
+  // they fit there (it is dead by then), else a region of their own
+  if (waves * d * asize <= H * tsize) {
+    const int MH = M * H * tsize;
+    const int dlt0 = lds_h ? nh * MH : ((nh - 1) & 1) * MH;
+    const int dlt1 = lds_h ? (nh + 1) * MH : (nh & 1) * MH;
+    L.red = L.big + ((((nh - 1) & 1) == 0) ? dlt1 : dlt0);
+  } else {
+    L.red = o;
+    o = align16(o + waves * M * d * asize);
+  }
   L.outp = o;
   o = align16(o + waves * M * asize);
   L.out = o;

@@ -86,7 +86,7 @@ struct MlpSmem {
   typename P::T* dlt1;
   typename InPrec<P>::type::T* thf;  // input t, B fragments of the input layer
   typename P::vec* gth;              // [M][d] d out / d t
-  typename P::acc* red;              // [kWaves][M][d] partial sums
+  typename P::acc* red;              // [kWaves][M][d] input-gradient partial sums
   typename P::acc* outp;             // [kWaves][M] output partial sums
   typename P::acc* out;              // [M]
   typename P::acc* up;               // [M] upstream gradient, NULL means 1
@@ -569,6 +569,9 @@ __device__ __forceinline__ void mlp_backward(const MlpParams& mp, const MlpSmem<
   // ---- d out / d t = W_1^T delta_1: the K = H k-steps are dealt to the waves round-robin
   // (wave w takes w, w + 8, ...) and the 8 partial tiles are summed in wave order; the
   // first row tile's leading fragments are loaded before the barrier ----
+  // per-wave partial sums (the layout places them in the delta buffer that does not hold
+  // delta_1 when they fit there)
+  acc* red = s.red;
   if (want_input_grad) {
     // delta_1 is the output of the last hidden-layer step above, or delta_L if nh == 1
     const T* d1 = (((nh - 1) & 1) == 0) ? s.dlt0 : s.dlt1;
@@ -607,15 +610,15 @@ __device__ __forceinline__ void mlp_backward(const MlpParams& mp, const MlpSmem<
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int i = rt * 16 + P::drow(g, r);
-          if (i < d) s.red[(wv * M + ct * 16 + cl) * d + i] = (acc)part[ct][r];
+          if (i < d) red[(wv * M + ct * 16 + cl) * d + i] = (acc)part[ct][r];
         }
     }
   }
   __syncthreads();
   if (want_input_grad) {
     for (int e = tid; e < M * d; e += kThreads) {
-      acc v = s.red[e];
-      for (int w = 1; w < kWaves; ++w) v += s.red[w * M * d + e];
+      acc v = red[e];
+      for (int w = 1; w < kWaves; ++w) v += red[w * M * d + e];
       s.gth[e] = (vec)v;
     }
   }
