@@ -1,0 +1,117 @@
+"""GPU edge cases against the FP64 oracle: the largest supported network shapes, the
+deepest network, single chains, empty calls, and the smallest AIES ensemble.
+
+Tolerances are those of test_gpu_parity.py (FP32: logL 2e-5 (1 + |logL|), gradient
+2e-4 (1 + |g|); BF16: the emulator term within 2e-2)."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2606_04895_amd as B
+from oracle import samplers as OS, target as OT, philox as OP
+from workloads import small_problem
+
+pytestmark = pytest.mark.gpu
+
+
+def _pts(prob, n, seed):
+    rng = np.random.default_rng(seed)
+    sd = np.sqrt(np.diag(prob["gauss_cov"]))
+    return prob["gauss_mean"] + rng.normal(size=(n, prob["d"])) * sd
+
+
+def _check(prob, prec, n, tl, tg):
+    ctx = B.best_init(prob, n_chains=16, precision=prec, seed=1)
+    x = _pts(prob, n, 3)
+    lp, g = B.best_logL_grad(ctx, x.T.copy())
+    lo, go = OT.log_target(prob, x)
+    assert np.all(np.isfinite(lp)) and np.all(np.isfinite(g))
+    assert np.max(np.abs(lp - lo) / (1 + np.abs(lo))) < tl
+    if tg is not None:
+        assert np.max(np.abs(g.T - go) / (1 + np.abs(go))) < tg
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec,tl,tg", [("bf16", 2e-2, None), ("fp32", 2e-5, 2e-4)])
+def test_widest_network_and_largest_d(prec, tl, tg):
+    """d = 32 (the largest input), width 2048 (BF16) / 1024 (FP32, whose 2048-wide
+    activation buffers exceed the LDS budget)."""
+    width = 2048 if prec == "bf16" else 1024
+    prob = small_problem(d=32, width=width, n_hidden=2, seed=13)
+    _check(prob, prec, 45, tl, tg)
+
+
+def test_width_beyond_lds_budget_is_rejected():
+    prob = small_problem(d=8, width=2048, n_hidden=2, seed=13)
+    with pytest.raises(B.BestError) as e:
+        B.best_init(prob, n_chains=16, precision="fp32", seed=1)
+    assert e.value.code == 1
+
+
+@pytest.mark.parametrize("prec,tl,tg", [("bf16", 2e-2, None), ("fp32", 2e-5, 2e-4)])
+def test_deepest_network(prec, tl, tg):
+    prob = small_problem(d=3, width=128, n_hidden=16, seed=17)
+    _check(prob, prec, 21, tl, tg)
+
+
+def test_empty_and_zero_step_calls():
+    prob = small_problem(d=4, width=128, n_hidden=2)
+    ctx = B.best_init(prob, n_chains=16, precision="fp32", seed=1)
+    x0 = B.best_get_state(ctx)[0]
+    empty = torch.empty((4, 0), dtype=torch.float64, device="cuda")
+    lp, g = B.best_logL_grad(ctx, empty)
+    assert lp.numel() == 0
+    st = B.best_step(ctx, "mala", 0, eps=0.1)
+    assert st["evals"] == 0 and st["accepted"] == 0
+    assert np.array_equal(B.best_get_state(ctx)[0], x0)
+
+
+def _one_step_oracle(prob, ctx, sampler, kw, seed):
+    """Oracle transition from the GPU's current state (same Philox streams)."""
+    t = B.best_get_step_counter(ctx)
+    x0, lp0, _ = B.best_get_state(ctx)
+    x0 = x0.T.copy()
+    if sampler == "aies":
+        new, info = OS.aies_step(prob, dict(x=x0, lp=OT.log_target(prob, x0)[0]), t, seed,
+                                 kw["stretch_a"])
+        return x0, new["x"], info
+    mu, L = B.best_get_whitening(ctx)
+    W = dict(mu=mu, L=L)
+    st = OS.init_state(prob, W, x0)
+    fn = dict(mh=OS.mh_step, mala=OS.mala_step, hmc=OS.hmc_step)[sampler]
+    args = dict(mh=(kw.get("mh_scale"),), mala=(kw.get("eps"),),
+                hmc=(kw.get("eps"), kw.get("n_leapfrog")))[sampler]
+    new, info = fn(prob, W, st, t, seed, *args)
+    return x0, W["mu"][None, :] + new["z"] @ W["L"].T, info
+
+
+def _lockstep_tiny(prob, n, sampler, kw, seed, steps=5):
+    ctx = B.best_init(prob, n_chains=n, precision="fp32", seed=seed, init="gaussian",
+                      init_point=prob["gauss_mean"], init_scale=0.05)
+    B.best_set_whitening(ctx, prob["gauss_mean"], np.linalg.cholesky(prob["closed_cov"]))
+    for _ in range(steps):
+        x0, x_or, info = _one_step_oracle(prob, ctx, sampler, kw, seed)
+        B.best_step(ctx, sampler, 1, **kw)
+        x1 = B.best_get_state(ctx)[0].T
+        bad = np.any(x1 != x0, axis=1) != info["accepted"]
+        if bad.any():  # only where the decision is within rounding of the threshold
+            assert np.all(np.abs(info["log_alpha"] - info["log_u"])[bad] < 1e-6)
+        ok = ~bad
+        scale = np.abs(x_or[ok]) + np.abs(x_or[ok] - x0[ok]) + 1e-12
+        assert np.all(np.abs(x1[ok] - x_or[ok]) / scale < 1e-4)
+    ctx.close()
+
+
+@pytest.mark.parametrize("sampler,kw", [("mh", dict(mh_scale=2.4 / np.sqrt(5))),
+                                        ("mala", dict(eps=0.008)),
+                                        ("hmc", dict(eps=0.07, n_leapfrog=5))])
+def test_single_chain_lockstep(sampler, kw):
+    """One chain (a tile with 15 empty slots) follows the oracle step for step."""
+    prob = small_problem(d=5, width=128, n_hidden=3, twist=True)
+    _lockstep_tiny(prob, 1, sampler, kw, 0xBE58)
+
+
+def test_two_walker_aies_lockstep():
+    """The smallest AIES ensemble: each walker's only partner is the other one."""
+    prob = small_problem(d=5, width=128, n_hidden=3, twist=True)
+    _lockstep_tiny(prob, 2, "aies", dict(stretch_a=2.0), 0xBE59)
