@@ -62,6 +62,9 @@ extern "C" {
 #define BEST_MALA 1 /* Metropolis-adjusted Langevin, Sec. 2.1 */
 #define BEST_HMC 2  /* Hamiltonian Monte Carlo, leapfrog, identity mass (Sec. 2.1-2.2) */
 #define BEST_AIES 3 /* affine-invariant ensemble sampler, stretch move (Sec. 2.3) */
+#define BEST_NUTS 4 /* No-U-Turn sampler, Hoffman & Gelman's efficient slice version,
+                       identity mass in whitened space (named among the samplers, Sec. 2.1) */
+#define BEST_NUTS_MAX_DEPTH 12
 
 /* ---- walker initialisation (Sec. 3.2) ---- */
 #define BEST_INIT_UNIFORM 0    /* uniform in the prior box */
@@ -132,16 +135,21 @@ typedef struct {
   float *record;          /* device [record_capacity][d][n_chains] x-space samples or NULL */
   int64_t record_capacity;
   int32_t adapt_eps;      /* 1: dual-averaging update of the step size after every step */
-  double target_accept;   /* dual-averaging target (e.g. 0.57 MALA, 0.8 HMC) */
+  double target_accept;   /* dual-averaging target (e.g. 0.57 MALA, 0.8 HMC / NUTS) */
+  int32_t max_depth;      /* NUTS maximum tree depth, 1 .. BEST_NUTS_MAX_DEPTH: at most
+                             2^max_depth - 1 evaluations per transition */
 } best_step_params;
 
 typedef struct {
   int64_t accepted;        /* accepted transitions summed over chains and steps */
-  int64_t evals;           /* emulator evaluations (logL or logL+grad) */
+  int64_t evals;           /* emulator evaluations (logL or logL+grad); NUTS: the leaves of
+                              every chain's trajectory (the idle slots of chains that
+                              stopped before others in their tile are not counted) */
   int64_t n_nonfinite;     /* proposals whose log pi was NaN (rejected) */
   int64_t n_oob;           /* proposals outside the prior box (rejected) */
   int64_t n_recorded;      /* record slots written */
-  double sum_accept_prob;  /* sum of min(1, alpha) */
+  double sum_accept_prob;  /* sum of min(1, alpha); NUTS: of the per-transition mean over
+                              leaves of min(1, exp(H0 - H)) */
   double ms;               /* wall time of the call's kernels (hipEvents) */
   double eps;              /* current step size after the call */
   double eps_bar;          /* dual-averaging averaged step size */
@@ -183,10 +191,13 @@ int64_t best_mlp_nparams(int32_t d, int32_t width, int32_t n_hidden);
 int best_logL_grad(best_ctx *h, const double *x, int64_t n, double *logL, double *grad,
                    uint32_t flags);
 
-/* Advance every chain n_steps transitions of `sampler` (BEST_MH / MALA / HMC / AIES).
- * Randomness: Philox4x32-10 keyed by the seed, counter = (chain, global step,
+/* Advance every chain n_steps transitions of `sampler` (BEST_MH / MALA / HMC / AIES /
+ * NUTS).  Randomness: Philox4x32-10 keyed by the seed, counter = (chain, global step,
  * stream << 24 | substep, block); the global step counter advances by n_steps.
- * out (may be NULL) receives the call's statistics; the call synchronises the stream. */
+ * out (may be NULL) receives the call's statistics; the call synchronises the stream.
+ * MALA, HMC and NUTS need a gradient precision other than BEST_FP64 (BEST_ESTATE).  The
+ * first NUTS call (or one with a deeper max_depth) allocates the trajectory buffers,
+ * (8 + 4 max_depth) d + 2 max_depth + 1 doubles per chain; BEST_ENOMEM if that fails. */
 int best_step(best_ctx *h, int32_t sampler, int64_t n_steps, const best_step_params *p,
               best_step_stats *out);
 

@@ -170,6 +170,8 @@ struct best_ctx {
   double *es_mean = nullptr, *es_ssq = nullptr, *es_part = nullptr;
   int64_t es_cap = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  double* nu_buf = nullptr;  // NUTS trajectory buffers (allocated by the first NUTS call)
+  NutsState nu{};
   std::vector<double> lower, upper;
   double mlp_coef = 0, offset = 0;
 };
@@ -469,7 +471,7 @@ int best_init(best_ctx** out, const best_problem* p, const best_config* c) {
   double** scal[] = {&S.lp, &S.lpp, &S.sum_prob, &S.step_prob};
   for (double** v : scal)
     if (h->mem.alloc(v, n1) != hipSuccess) return bail(fail(h, BEST_ENOMEM, "state allocation"));
-  uint32_t** cnt[] = {&S.n_acc, &S.n_nonfinite, &S.n_oob};
+  uint32_t** cnt[] = {&S.n_acc, &S.n_nonfinite, &S.n_oob, &S.n_evals};
   for (uint32_t** v : cnt)
     if (h->mem.alloc(v, n1) != hipSuccess) return bail(fail(h, BEST_ENOMEM, "state allocation"));
   for (double** v : vecs)
@@ -554,11 +556,50 @@ int best_logL_grad(best_ctx* h, const double* x, int64_t n, double* logL, double
   return BEST_OK;
 }
 
+// NUTS buffers for trees of up to `depth` levels, carved from one allocation.
+static int ensure_nuts(best_ctx* h, int depth) {
+  if (h->nu_buf && h->nu.max_depth >= depth) return BEST_OK;
+  h->mem.release(h->nu_buf);
+  h->nu_buf = nullptr;
+  h->nu = NutsState{};
+  const size_t nd = (size_t)h->Np * h->d, n1 = (size_t)h->Np;
+  const size_t total = nd * (8 + 4 * (size_t)depth) + n1 * (2 * (size_t)depth + 1);
+  if (h->mem.alloc(&h->nu_buf, total) != hipSuccess)
+    return fail(h, BEST_ENOMEM, "NUTS trajectory buffers");
+  double* b = h->nu_buf;
+  auto take = [&](size_t n) {
+    double* r = b;
+    b += n;
+    return r;
+  };
+  NutsState& U = h->nu;
+  U.zm = take(nd);
+  U.qm = take(nd);
+  U.gm = take(nd);
+  U.zpl = take(nd);
+  U.qpl = take(nd);
+  U.gpl = take(nd);
+  U.xc = take(nd);
+  U.gxc = take(nd);
+  U.lpc = take(n1);
+  U.pz = take(nd * depth);
+  U.pq = take(nd * depth);
+  U.px = take(nd * depth);
+  U.pgx = take(nd * depth);
+  U.plp = take(n1 * depth);
+  U.pn = take(n1 * depth);
+  U.max_depth = depth;
+  return BEST_OK;
+}
+
 int best_step(best_ctx* h, int32_t sampler, int64_t n_steps, const best_step_params* p,
               best_step_stats* out) {
   if (!h) return BEST_EINVAL;
+  int rc;
   if (!p) return fail(h, BEST_EINVAL, "params is NULL");
-  if (sampler < BEST_MH || sampler > BEST_AIES) return fail(h, BEST_EINVAL, "unknown sampler");
+  if (sampler < BEST_MH || sampler > BEST_NUTS) return fail(h, BEST_EINVAL, "unknown sampler");
+  if (sampler == BEST_NUTS && (p->max_depth < 1 || p->max_depth > BEST_NUTS_MAX_DEPTH))
+    return fail(h, BEST_EINVAL, "max_depth must be in 1 .. BEST_NUTS_MAX_DEPTH");
   if (n_steps < 0) return fail(h, BEST_EINVAL, "n_steps < 0");
   if (p->thin < 1) return fail(h, BEST_EINVAL, "thin must be >= 1");
   if (p->record && p->record_capacity < 0) return fail(h, BEST_EINVAL, "record_capacity < 0");
@@ -567,22 +608,23 @@ int best_step(best_ctx* h, int32_t sampler, int64_t n_steps, const best_step_par
   if (sampler == BEST_AIES && !(p->stretch_a > 1.0)) return fail(h, BEST_EINVAL, "stretch_a must be > 1");
   if (sampler == BEST_AIES && (h->N < 2 || (h->N & 1)))
     return fail(h, BEST_ESTATE, "AIES needs an even number of walkers >= 2");
-  if (p->adapt_eps && sampler != BEST_MALA && sampler != BEST_HMC)
-    return fail(h, BEST_EINVAL, "step-size adaptation applies to MALA and HMC");
+  if (p->adapt_eps && sampler != BEST_MALA && sampler != BEST_HMC && sampler != BEST_NUTS)
+    return fail(h, BEST_EINVAL, "step-size adaptation applies to MALA, HMC and NUTS");
   if (p->adapt_eps && !(p->target_accept > 0 && p->target_accept < 1))
     return fail(h, BEST_EINVAL, "target_accept must be in (0, 1)");
-  int rc;
-  const bool gradient = sampler == BEST_MALA || sampler == BEST_HMC;
+  const bool gradient = sampler == BEST_MALA || sampler == BEST_HMC || sampler == BEST_NUTS;
   if (gradient && h->prec == BEST_FP64)
     return fail(h, BEST_ESTATE,
-                "MALA/HMC with FP64 GEMMs is switched off: an earlier build of this path "
+                "MALA/HMC/NUTS with FP64 GEMMs is switched off: an earlier build of this path "
                 "faulted on the GPU and the cause has not been shown yet");
+  if (sampler == BEST_NUTS && (rc = ensure_nuts(h, p->max_depth))) return rc;
   if (sampler != BEST_AIES && h->z_stale && (rc = rewhiten(h))) return rc;
   if (gradient && h->gx_stale && (rc = refresh_state(h))) return rc;
   const size_t n1 = (size_t)h->Np;
   HIPCHK(h, hipMemsetAsync(h->st.n_acc, 0, n1 * 4, h->stream));
   HIPCHK(h, hipMemsetAsync(h->st.n_nonfinite, 0, n1 * 4, h->stream));
   HIPCHK(h, hipMemsetAsync(h->st.n_oob, 0, n1 * 4, h->stream));
+  HIPCHK(h, hipMemsetAsync(h->st.n_evals, 0, n1 * 4, h->stream));
   HIPCHK(h, hipMemsetAsync(h->st.sum_prob, 0, n1 * 8, h->stream));
   if (p->adapt_eps) {
     // keep the running dual-averaging state; only the target can change between calls
@@ -602,6 +644,10 @@ int best_step(best_ctx* h, int32_t sampler, int64_t n_steps, const best_step_par
   a.rec_pitch = h->N;
   a.eps = p->eps;
   a.eps_ptr = (p->adapt_eps || !(p->eps > 0)) ? h->da + 4 : nullptr;
+  if (sampler == BEST_NUTS) {
+    a.nu = h->nu;
+    a.nu.max_depth = p->max_depth;
+  }
   const int64_t M = 16 * h->MT;
   const size_t lds = h->lds.total;
   if (sampler == BEST_AIES) {
@@ -636,7 +682,7 @@ int best_step(best_ctx* h, int32_t sampler, int64_t n_steps, const best_step_par
   HIPCHK(h, launch_stats(h->st, h->st_i, h->st_d, h->stream));
   int64_t si[4] = {0, 0, 0, 0};
   double sd[4] = {0, 0, 0, 0}, da[9];
-  HIPCHK(h, hipMemcpyAsync(si, h->st_i, 3 * sizeof(int64_t), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipMemcpyAsync(si, h->st_i, 4 * sizeof(int64_t), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipMemcpyAsync(sd, h->st_d, sizeof(double), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipMemcpyAsync(da, h->da, 9 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
@@ -651,7 +697,7 @@ int best_step(best_ctx* h, int32_t sampler, int64_t n_steps, const best_step_par
     out->n_nonfinite = si[1];
     out->n_oob = si[2];
     out->sum_accept_prob = sd[0];
-    out->evals = n_steps * h->N * per;
+    out->evals = sampler == BEST_NUTS ? si[3] : n_steps * h->N * per;
     out->n_recorded = p->record ? std::min<int64_t>(n_steps / p->thin, p->record_capacity) : 0;
     out->ms = ms;
     out->eps = (p->adapt_eps || !(p->eps > 0)) ? da[4] : p->eps;

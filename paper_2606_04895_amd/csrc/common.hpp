@@ -138,7 +138,13 @@ __device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint
   return U4{c0, c1, c2, c3};
 }
 
-enum Stream : uint32_t { kStreamNormal = 1, kStreamAccept = 2, kStreamAies = 3, kStreamInit = 4 };
+enum Stream : uint32_t {
+  kStreamNormal = 1,
+  kStreamAccept = 2,
+  kStreamAies = 3,
+  kStreamInit = 4,
+  kStreamNuts = 5
+};
 
 struct Rng {
   uint32_t k0, k1;

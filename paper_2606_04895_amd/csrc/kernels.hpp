@@ -1,5 +1,5 @@
 // Fused per-chain-tile kernels: target evaluation (FP64 assembly around the MLP emulator)
-// and the MH / MALA / HMC / AIES transitions.  Templated on the GEMM precision P and the
+// and the MH / MALA / HMC / AIES / NUTS transitions.  Templated on the GEMM precision P and the
 // chain-tile width M = 16*MT; instantiated once per precision in kernels_<prec>.hip.
 #pragma once
 #include "mlp_tile.hpp"
@@ -34,7 +34,21 @@ struct State {
   double *x, *z, *gx, *lp;
   double *xp, *zp, *gxp, *lpp, *q, *gz, *gzp;
   uint32_t *n_acc, *n_nonfinite, *n_oob;
+  uint32_t* n_evals;  // emulator evaluations per chain (samplers whose count varies: NUTS)
   double *sum_prob, *step_prob;
+};
+
+// NUTS trajectory state (global memory; one chain's d components contiguous, element
+// (c, i) at [c * d + i] of a [Np][d] array, so that a lane group holding one chain reads
+// them in one pass): the tree ends (whitened position, momentum, whitened gradient), the
+// tree's candidate (x, grad_x, log pi) and, per subtree level 0 .. max_depth - 1, the
+// pending left sibling (its first leaf's z and q, its candidate, its valid-point count).
+struct NutsState {
+  double *zm, *qm, *gm, *zpl, *qpl, *gpl;  // [Np][d]
+  double *xc, *gxc, *lpc;                  // [Np][d], [Np][d], [Np]
+  double *pz, *pq, *px, *pgx;              // [max_depth][Np][d]
+  double *plp, *pn;                        // [max_depth][Np]
+  int max_depth;
 };
 
 // Byte offsets into dynamic LDS (computed on the host by lds_layout()).
@@ -118,6 +132,7 @@ struct KArgs {
   int aies_half;
   void* hsave;
   int64_t hsave_stride;  // elements of acc per workgroup
+  NutsState nu;
   // best_logL_grad
   const double* ex_x;
   int64_t ex_pitch;
@@ -680,6 +695,247 @@ __device__ __forceinline__ void aies_tile(const KArgs& a, char* smem, typename P
   __syncthreads();
 }
 
+// ---------------------------------------------------------------------------------------
+// No-U-Turn sampler (Hoffman & Gelman's efficient slice version) for a tile of chains, in
+// the whitened space with identity mass.  The recursive tree build is run iteratively and in
+// lockstep over the tile: doubling j appends 2^j leaves on the side v = +-1 drawn for each
+// chain; after leaf k, the subtrees that leaf completes (one per trailing one-bit of k) are
+// merged with the pending left siblings kept per level.  Chains that stop (U-turn,
+// divergence, maximum depth) idle until every chain of the tile has stopped; every leaf is
+// one emulator evaluation with gradient.
+//
+// Per-chain work runs on lane groups: dp = the smallest power of two >= d consecutive lanes
+// hold one chain's components (a wave holds 64 / dp chains) and dot products over the
+// components are butterfly sums within the group, which leave the identical value in every
+// lane of the group, so all of a group's lanes take the same decisions.
+//
+// Random numbers per step t and chain (Philox counters): momentum normals(stream 1, sub 0);
+// slice variable u = the accept uniform (stream 2, sub 0); doubling j: block(stream 5,
+// sub j, 0), first uniform < 1/2 -> v = -1 else +1, second uniform decides whether the
+// finished subtree's candidate replaces the tree's (iff < n' / n); merging two siblings into
+// a subtree of 2^l leaves that ends at leaf k of doubling j: block(stream 5, sub 16 + j,
+// 8 k + l), first uniform < n2 / (n1 + n2) takes the second sibling's candidate.
+// A leaf outside the prior box has log pi = -inf (never valid, and it stops the trajectory);
+// the dynamics use the unbounded gradient, as in the HMC transition.  The acceptance
+// statistic for step-size adaptation is the mean of min(1, exp(H0 - H)) over the leaves.
+// ---------------------------------------------------------------------------------------
+constexpr double kNutsDeltaMax = 1000.0;  // divergence threshold on the energy error
+
+__device__ __forceinline__ double group_sum(double v, int dp) {
+  for (int o = dp >> 1; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <class P, int MT>
+__device__ __forceinline__ void nuts_tile(const KArgs& a, char* smem, typename P::acc* hsave,
+                                          int64_t c0, int mv, uint64_t t, double eps) {
+  constexpr int M = 16 * MT;
+  const State& S = a.st;
+  const NutsState& U = a.nu;
+  const int64_t Np = S.Np;
+  const int d = a.tg.d, tid = local_tid();
+  const double* Lw = a.wh.L;
+  const Scratch T = tile_scratch<MT>(a, smem, c0);
+  const TView GX{S.gx + c0, Np};
+  int* inbox = (int*)(smem + a.lds.mi);
+  int* alive = inbox + 2 * M;
+  int* moved = inbox + 3 * M;
+  double* md = (double*)(smem + a.lds.md);
+  double* h0 = md;              // H(z0, q0)
+  double* lslice = md + M;      // log u - H(z0, q0)
+  double* nvalid = md + 2 * M;  // valid points of the tree so far
+  double* stat = md + 3 * M;    // sum over leaves of min(1, exp(H0 - H))
+  double* nleaf = md + 4 * M;   // leaves (evaluations) of the trajectory
+  double* dir = md + 5 * M;     // direction of the current doubling
+  double* utop = md + 6 * M;    // the doubling's candidate-replacement uniform
+  int lg = 0;
+  while ((1 << lg) < d) ++lg;
+  const int dp = 1 << lg, gi = tid & (dp - 1), gstep = kThreads >> lg;
+  const bool on = gi < d;
+  auto row = [&](int64_t ch) { return ch * d + gi; };
+  auto lvl = [&](int l, int64_t ch) { return ((int64_t)l * Np + ch) * d + gi; };
+
+  tile_whiten(a.wh.mu, Lw, d, mv, TView{S.x + c0, Np}, T.z);
+  for (int c = tid >> lg; c < mv; c += gstep) {
+    const int64_t ch = c0 + c;
+    double q = 0;
+    if (on) {
+      q = normal_dim(a.rng, ch, t, kStreamNormal, 0, gi);
+      const double z = T.z(gi, c), g = lt_dot(Lw, d, gi, GX, c);
+      const int64_t o = row(ch);
+      U.zm[o] = z;
+      U.zpl[o] = z;
+      U.qm[o] = q;
+      U.qpl[o] = q;
+      U.gm[o] = g;
+      U.gpl[o] = g;
+    }
+    const double kin = group_sum(q * q, dp);
+    if (gi == 0) {
+      const double hh = -S.lp[ch] + 0.5 * kin;
+      h0[c] = hh;
+      lslice[c] = log(accept_uniform(a.rng, ch, t, 0)) - hh;
+      nvalid[c] = 1.0;
+      stat[c] = 0.0;
+      nleaf[c] = 0.0;
+      alive[c] = 1;
+      moved[c] = 0;
+    }
+  }
+  for (int c = mv + tid; c < M; c += kThreads) alive[c] = 0;
+  __syncthreads();
+
+  bool any = true;
+  for (int j = 0; j < U.max_depth && any; ++j) {
+    for (int c = tid; c < mv; c += kThreads) {
+      if (!alive[c]) continue;
+      const U4 b = a.rng.block(c0 + c, t, kStreamNuts, (uint32_t)j, 0);
+      dir[c] = u52(b.x, b.y) < 0.5 ? -1.0 : 1.0;
+      utop[c] = u52(b.z, b.w);
+    }
+    __syncthreads();
+    const int nk = 1 << j;
+    for (int k = 0; k < nk; ++k) {
+      // half kick and drift from the tree end on the chain's side
+      for (int c = tid >> lg; c < mv; c += gstep) {
+        if (!alive[c] || !on) continue;
+        const int64_t o = row(c0 + c);
+        const double v = dir[c];
+        const bool lo = v < 0.0;
+        const double qe = lo ? U.qm[o] : U.qpl[o];
+        const double ge = lo ? U.gm[o] : U.gpl[o];
+        const double ze = lo ? U.zm[o] : U.zpl[o];
+        const double qh = qe + (0.5 * v) * eps * ge;
+        T.q(gi, c) = qh;
+        T.zp(gi, c) = ze + v * eps * qh;
+      }
+      __syncthreads();
+      tile_affine(a.wh.mu, Lw, d, M, mv, T.zp, T.xp);
+      __syncthreads();
+      eval_tile<P, MT>(a, smem, hsave, T.xp, mv, T.lpp, T.gxp, true, false);
+      // second half kick, the leaf's bookkeeping, subtree merges
+      const int nmerge = __builtin_ctz(~(unsigned)k);  // trailing one-bits of k (<= j)
+      for (int c = tid >> lg; c < mv; c += gstep) {
+        if (!alive[c]) continue;
+        const int64_t ch = c0 + c;
+        const double v = dir[c];
+        const bool lo = v < 0.0;
+        double z = 0, q = 0, xl = 0, gxl = 0;
+        if (on) {
+          const double g = lt_dot(Lw, d, gi, T.gxp, c);
+          q = T.q(gi, c) + (0.5 * v) * eps * g;
+          z = T.zp(gi, c);
+          xl = T.xp(gi, c);
+          gxl = T.gxp(gi, c);
+          const int64_t o = row(ch);
+          (lo ? U.zm : U.zpl)[o] = z;
+          (lo ? U.qm : U.qpl)[o] = q;
+          (lo ? U.gm : U.gpl)[o] = g;
+        }
+        const double kin = group_sum(q * q, dp);
+        const int ib = inbox[c];
+        const double lp = ib ? T.lpp[c] : -INFINITY;
+        const double h = -lp + 0.5 * kin;
+        const double ls = lslice[c];
+        bool go = ls < -h + kNutsDeltaMax;
+        double ncur = (ls <= -h) ? 1.0 : 0.0;
+        if (gi == 0) {
+          nleaf[c] += 1.0;
+          stat[c] += isfinite(h) ? exp(fmin(0.0, h0[c] - h)) : 0.0;
+          if (!ib) S.n_oob[ch] += 1u;
+          if (isnan(lp)) S.n_nonfinite[ch] += 1u;
+        }
+        // candidate / first-leaf source of the current subtree: -1 the leaf, l >= 0 the
+        // pending left sibling of level l
+        int csrc = -1, fsrc = -1;
+        for (int l = 0; l < nmerge && go; ++l) {
+          const double nl = U.pn[(int64_t)l * Np + ch];
+          const U4 b = a.rng.block(ch, t, kStreamNuts, 16u + (uint32_t)j,
+                                   (uint32_t)(8 * k + l + 1));
+          const double tot = nl + ncur;
+          if (!(tot > 0.0 && u52(b.x, b.y) < ncur / tot)) csrc = l;
+          ncur = tot;
+          double pzv = 0, pqv = 0;
+          if (on) {
+            pzv = U.pz[lvl(l, ch)];
+            pqv = U.pq[lvl(l, ch)];
+          }
+          const double dz = v * (z - pzv);
+          const double s1 = group_sum(dz * pqv, dp), s2 = group_sum(dz * q, dp);
+          go = s1 >= 0.0 && s2 >= 0.0;
+          fsrc = l;
+        }
+        if (go && nmerge < j) {
+          // the subtree becomes the pending left sibling of its level
+          if (on) {
+            const int64_t o = lvl(nmerge, ch);
+            U.pz[o] = fsrc < 0 ? z : U.pz[lvl(fsrc, ch)];
+            U.pq[o] = fsrc < 0 ? q : U.pq[lvl(fsrc, ch)];
+            U.px[o] = csrc < 0 ? xl : U.px[lvl(csrc, ch)];
+            U.pgx[o] = csrc < 0 ? gxl : U.pgx[lvl(csrc, ch)];
+          }
+          if (gi == 0) {
+            const int64_t o = (int64_t)nmerge * Np + ch;
+            U.plp[o] = csrc < 0 ? lp : U.plp[(int64_t)csrc * Np + ch];
+            U.pn[o] = ncur;
+          }
+        } else if (go) {
+          // doubling j complete: progressive sampling of the tree's candidate
+          const double nv = nvalid[c];
+          if (utop[c] < ncur / nv) {
+            if (on) {
+              const int64_t o = row(ch);
+              U.xc[o] = csrc < 0 ? xl : U.px[lvl(csrc, ch)];
+              U.gxc[o] = csrc < 0 ? gxl : U.pgx[lvl(csrc, ch)];
+            }
+            if (gi == 0) {
+              U.lpc[ch] = csrc < 0 ? lp : U.plp[(int64_t)csrc * Np + ch];
+              moved[c] = 1;
+            }
+          }
+          if (gi == 0) nvalid[c] = nv + ncur;
+          // U-turn of the whole trajectory (this side's end is the leaf just made)
+          double zmv = 0, qmv = 0, zpv = 0, qpv = 0;
+          if (on) {
+            const int64_t o = row(ch);
+            zmv = lo ? z : U.zm[o];
+            qmv = lo ? q : U.qm[o];
+            zpv = lo ? U.zpl[o] : z;
+            qpv = lo ? U.qpl[o] : q;
+          }
+          const double dz = zpv - zmv;
+          const double s1 = group_sum(dz * qmv, dp), s2 = group_sum(dz * qpv, dp);
+          go = s1 >= 0.0 && s2 >= 0.0;
+        }
+        if (gi == 0 && !go) alive[c] = 0;
+      }
+      __syncthreads();
+      any = false;
+      for (int c = 0; c < mv && !any; ++c) any = alive[c] != 0;
+      if (!any) break;
+    }
+  }
+
+  // the tree's candidate becomes the new state; per-chain statistics
+  for (int c = tid >> lg; c < mv; c += gstep) {
+    const int64_t ch = c0 + c;
+    if (moved[c] && on) {
+      S.x[gi * Np + ch] = U.xc[row(ch)];
+      S.gx[gi * Np + ch] = U.gxc[row(ch)];
+    }
+    if (gi == 0) {
+      const double nl = nleaf[c];
+      const double pr = nl > 0.0 ? stat[c] / nl : 0.0;
+      if (moved[c]) S.lp[ch] = U.lpc[ch];
+      S.n_acc[ch] += moved[c] ? 1u : 0u;
+      S.sum_prob[ch] += pr;
+      S.step_prob[ch] = pr;
+      S.n_evals[ch] += (uint32_t)nl;
+    }
+  }
+  __syncthreads();
+}
+
 // Copy the launch's small constant arrays (whitening, Gaussian part, box, input scaling)
 // into LDS and point the kernel's argument copy at them; they are read in every phase of
 // every step.
@@ -737,6 +993,7 @@ __global__ __launch_bounds__(kThreads, 1) void step_kernel(KArgs a) {
       if constexpr (SAMPLER == 1) mala_tile<P, MT>(a, smem, hsave, c0, mv, t, eps);
       if constexpr (SAMPLER == 2) hmc_tile<P, MT>(a, smem, hsave, c0, mv, t, eps);
       if constexpr (SAMPLER == 3) aies_tile<P, MT>(a, smem, hsave, c0, mv, t);
+      if constexpr (SAMPLER == 4) nuts_tile<P, MT>(a, smem, hsave, c0, mv, t, eps);
       if constexpr (SAMPLER != 3) record_tile(a, s, a.tg.d, M, mv, c0);
     }
   }

@@ -81,21 +81,24 @@ __global__ void da_update_kernel(const double* step_prob, int64_t N, double* da)
 // ---- per-call statistics: [accepted, nonfinite, oob] int64 + [sum_prob] -----------------
 __global__ void stats_kernel(State S, int64_t* out_i, double* out_d) {
   __shared__ double sh[kAuxThreads];
-  double a = 0, nf = 0, oob = 0, sp = 0;
+  double a = 0, nf = 0, oob = 0, ne = 0, sp = 0;
   for (int64_t c = threadIdx.x; c < S.N; c += kAuxThreads) {
     a += S.n_acc[c];
     nf += S.n_nonfinite[c];
     oob += S.n_oob[c];
+    ne += S.n_evals[c];
     sp += S.sum_prob[c];
   }
   a = block_sum(a, sh);
   nf = block_sum(nf, sh);
   oob = block_sum(oob, sh);
+  ne = block_sum(ne, sh);
   sp = block_sum(sp, sh);
   if (threadIdx.x == 0) {
     out_i[0] = (int64_t)a;
     out_i[1] = (int64_t)nf;
     out_i[2] = (int64_t)oob;
+    out_i[3] = (int64_t)ne;
     out_d[0] = sp;
   }
 }

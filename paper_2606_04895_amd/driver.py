@@ -20,8 +20,8 @@ import numpy as np
 from . import (best_adapt, best_ess, best_init, best_logL_grad, best_set_mlp,
                best_set_step_size, best_standardise, best_step, Trainer)
 
-TARGET_ACCEPT = {"mala": 0.57, "hmc": 0.8}
-EPS0 = {"mala": 0.5, "hmc": 0.3}
+TARGET_ACCEPT = {"mala": 0.57, "hmc": 0.8, "nuts": 0.8}
+EPS0 = {"mala": 0.5, "hmc": 0.3, "nuts": 0.5}
 
 
 def window_plan(warmup, schedule="doubling", first=10):
@@ -54,17 +54,17 @@ def window_plan(warmup, schedule="doubling", first=10):
 # Default window schedule per sampler (measured on the c2 workload from a uniform start in
 # the prior box): MALA and MH need the short early windows to follow the contracting
 # ensemble; HMC reaches the typical set within the first window and tunes its step size
-# better over the long windows.
-SCHEDULE = {"mala": "doubling", "mh": "doubling", "hmc": "thirds"}
+# better over the long windows; NUTS takes HMC's schedule.
+SCHEDULE = {"mala": "doubling", "mh": "doubling", "hmc": "thirds", "nuts": "thirds"}
 
 
 def burn_in(ctx, sampler, warmup, d, n, n_leap=10, mh_scale=None, stretch_a=2.0,
-            schedule=None):
+            schedule=None, max_depth=8):
     import torch
 
     schedule = schedule or SCHEDULE.get(sampler, "doubling")
 
-    kw = dict(n_leapfrog=n_leap, stretch_a=stretch_a,
+    kw = dict(n_leapfrog=n_leap, stretch_a=stretch_a, max_depth=max_depth,
               mh_scale=mh_scale if mh_scale else 2.4 / np.sqrt(d))
     t0 = time.perf_counter()
     if sampler == "aies":
@@ -93,11 +93,12 @@ def burn_in(ctx, sampler, warmup, d, n, n_leap=10, mh_scale=None, stretch_a=2.0,
     return time.perf_counter() - t0
 
 
-def sample(ctx, sampler, steps, d, n, n_leap=10, mh_scale=None, stretch_a=2.0, ess=True):
+def sample(ctx, sampler, steps, d, n, n_leap=10, mh_scale=None, stretch_a=2.0, ess=True,
+           max_depth=8):
     """Timed production run with every step recorded; returns (stats, record, wall_s, ess)."""
     import torch
 
-    kw = dict(n_leapfrog=n_leap, stretch_a=stretch_a,
+    kw = dict(n_leapfrog=n_leap, stretch_a=stretch_a, max_depth=max_depth,
               mh_scale=mh_scale if mh_scale else 2.4 / np.sqrt(d))
     rec = torch.empty((steps, d, n), dtype=torch.float32, device="cuda")
     torch.cuda.synchronize()
