@@ -7,7 +7,9 @@ For one parameter with M chains of length T (x_{m,t}):
     rho_0 = 1,  rho_t = 1 - (W - mean_m gamma_{m,t}) / var+    (t >= 1)
 Geyer (1992) initial positive sequence on pair sums P_k = rho_{2k} + rho_{2k+1}: keep
 k = 0, 1, ... while P_k > 0, then make the kept P_k non-increasing (initial monotone);
-    tau = -1 + 2 sum_k P_k,   ESS = M T / tau.
+    tau = max(-1 + 2 sum_k P_k, 1 / log10(M T)),   ESS = M T / tau.
+The floor on tau (as in Stan; Vehtari et al. 2021) bounds ESS by M T log10(M T) for
+antithetic chains, where the truncated sum can fall below 1/2 and tau would go negative.
 The autocovariances are computed here with numpy's FFT (zero-padded to avoid wrap-around).
 """
 from __future__ import annotations
@@ -39,7 +41,7 @@ def rho_hat(x):
     return rho
 
 
-def geyer_tau(rho):
+def geyer_tau(rho, n_draws):
     T = rho.shape[0]
     sums = []
     k = 0
@@ -51,13 +53,13 @@ def geyer_tau(rho):
         k += 1
     for i in range(1, len(sums)):
         sums[i] = min(sums[i], sums[i - 1])
-    return -1.0 + 2.0 * float(np.sum(sums))
+    return max(-1.0 + 2.0 * float(np.sum(sums)), 1.0 / np.log10(n_draws))
 
 
 def ess(x):
     """x (M, T) one parameter -> ESS."""
     M, T = np.shape(x)
-    return M * T / geyer_tau(rho_hat(x))
+    return M * T / geyer_tau(rho_hat(x), M * T)
 
 
 def min_ess(samples):

@@ -69,6 +69,14 @@ def test_ess_of_ar1_chains(rho):
     assert abs(e / ref - 1) < 0.08
 
 
+def test_ess_of_exactly_alternating_chains_hits_the_tau_floor():
+    """x_t = (-1)^t: rho_1 = -1 makes the first pair sum 0, the truncated Geyer sum is
+    empty and tau would be -1; the floor 1 / log10(M T) gives ESS = M T log10(M T)."""
+    M, T = 8, 200
+    x = np.tile(np.where(np.arange(T) % 2 == 0, 1.0, -1.0), (M, 1))
+    assert ess.ess(x) == pytest.approx(M * T * np.log10(M * T), rel=1e-12)
+
+
 def test_first_adam_step_closed_form():
     rng = np.random.default_rng(2)
     p = rng.normal(size=10)
