@@ -224,9 +224,44 @@ int best_set_mlp(best_ctx *h, const double *params, double mlp_coef, double offs
 
 /* Multi-chain effective sample size of a record ([T][d][n_chains] device floats) per
  * parameter: rho_t = 1 - (W - mean_m gamma_{m,t}) / var+, Geyer initial monotone
- * sequence, ESS = M T / tau.  Autocovariances are summed directly on the device in FP64.
+ * sequence, tau = max(-1 + 2 sum P_k, 1 / log10(M T)), ESS = M T / tau.  Autocovariances
+ * are summed directly on the device in FP64.
  * ess_out: host [d]. */
 int best_ess(best_ctx *h, const float *record, int64_t T, double *ess_out);
+
+/* ---- convergence metrics (Sec. 4.1) ----
+ * Samples are device records [T][d][n_chains] (floats, chain fastest), as best_step writes
+ * them; d is the context's.  Results are host scalars / arrays; each call allocates its
+ * device scratch, synchronises the stream and frees it. */
+
+/* Gelman-Rubin type statistic of Sec. 4.1: B = covariance of the chain means (unbiased),
+ * W = mean of the chain covariances (unbiased); with D = diag(sqrt(B_ii)),
+ * R - 1 = max |eigenvalue| of (D^-1 W D^-1)^-1 (D^-1 B D^-1), written to *rminus1.
+ * T >= 2, n_chains >= 2.  BEST_EINVAL if some B_ii is 0 (identical chain means),
+ * BEST_ENOTPD if the normalised W is not positive definite. */
+int best_rhat(best_ctx *h, const float *samples, int64_t T, int64_t n_chains, double *rminus1);
+
+/* Credible limits and the credible metric of Sec. 4.1.  lo / hi (host [d], may be NULL):
+ * equal-tailed limits of every parameter at level alpha, the sample quantiles at
+ * (1 - alpha)/2 and 1 - (1 - alpha)/2 of the T n_chains draws (rule: h = (n - 1) p,
+ * k = floor(h), v_k + (h - k)(v_{k+1} - v_k) over the sorted values v).  With mu and L
+ * (host [d] and [d*d] row-major lower triangle, positive diagonal) the draws are whitened
+ * first, z = L^-1 (x - mu).  With ref_lo / ref_hi (host [d], the reference limits in the
+ * same coordinates) *metric = max_i (|hi_i - ref_hi_i| + |lo_i - ref_lo_i|) /
+ * (ref_hi_i - ref_lo_i).  At most 2^31 - 1 draws. */
+int best_credible(best_ctx *h, const float *samples, int64_t T, int64_t n_chains, double alpha,
+                  const double *mu, const double *L, const double *ref_lo,
+                  const double *ref_hi, double *lo, double *hi, double *metric);
+
+/* Sliced Wasserstein distance of Sec. 4.1 between sample sets a ([Ta][d][chains_a]) and b
+ * ([Tb][d][chains_b]): the mean over n_proj fixed unit directions w_k of the 1-d
+ * Wasserstein-1 distance between the projected draws, integral |F_a - F_b| over the merged
+ * sorted projections.  w_k = xi / |xi| with xi the d normals of Philox (key proj_seed,
+ * counter (k, 0, stream 6, 0)), so equal seeds give the same directions in every call.
+ * Optional whitening (mu, L) as for best_credible.  At most 2^31 - 1 draws in total. */
+int best_sliced_wasserstein(best_ctx *h, const float *a, int64_t Ta, int64_t chains_a,
+                            const float *b, int64_t Tb, int64_t chains_b, int32_t n_proj,
+                            uint64_t proj_seed, const double *mu, const double *L, double *out);
 
 /* ---- learned emulator (training on plain-model pairs) ---- */
 

@@ -920,7 +920,8 @@ int best_ess(best_ctx* h, const float* record, int64_t T, double* ess_out) {
         if (q > 0) sums[q] = std::min(sums[q], sums[q - 1]);
         s += sums[q];
       }
-      tau[i] = -1.0 + 2.0 * s;
+      // floor 1 / log10(N T): antithetic chains can make the truncated sum fall below 1/2
+      tau[i] = std::max(-1.0 + 2.0 * s, 1.0 / std::log10((double)N * (double)T));
       done[i] = 1;
     }
     if (all) break;
@@ -928,6 +929,284 @@ int best_ess(best_ctx* h, const float* record, int64_t T, double* ess_out) {
   for (int i = 0; i < d; ++i) ess_out[i] = (double)N * (double)T / tau[i];
   return BEST_OK;
 }
+
+// ---------------------------------------------------------------------------------------
+// Convergence metrics (Sec. 4.1)
+// ---------------------------------------------------------------------------------------
+}  // extern "C"
+
+namespace {
+
+struct DevBuf {  // temporary device buffer of one metric call
+  void* p = nullptr;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  hipError_t alloc(size_t bytes) { return hipMalloc(&p, bytes ? bytes : 16); }
+  double* f64() const { return (double*)p; }
+  int* i32() const { return (int*)p; }
+};
+
+// Eigenvalues of a symmetric d x d matrix (row-major, overwritten) by cyclic Jacobi rotations
+// (Golub & Van Loan, Matrix Computations, Sec. 8.5), sweeping until the off-diagonal mass is
+// below 1e-30 of the total.
+void sym_eigenvalues(std::vector<double>& A, int d, std::vector<double>& ev) {
+  for (int sweep = 0; sweep < 64; ++sweep) {
+    double off = 0, tot = 0;
+    for (int i = 0; i < d; ++i)
+      for (int j = 0; j < d; ++j) {
+        const double v = A[i * d + j] * A[i * d + j];
+        tot += v;
+        if (i != j) off += v;
+      }
+    if (off <= 1e-30 * tot) break;
+    for (int p = 0; p < d; ++p)
+      for (int q = p + 1; q < d; ++q) {
+        const double apq = A[p * d + q];
+        if (apq == 0.0) continue;
+        const double tau = (A[q * d + q] - A[p * d + p]) / (2.0 * apq);
+        const double t = (tau >= 0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(tau * tau + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+        for (int k = 0; k < d; ++k) {
+          const double akp = A[k * d + p], akq = A[k * d + q];
+          A[k * d + p] = c * akp - s * akq;
+          A[k * d + q] = s * akp + c * akq;
+        }
+        for (int k = 0; k < d; ++k) {
+          const double apk = A[p * d + k], aqk = A[q * d + k];
+          A[p * d + k] = c * apk - s * aqk;
+          A[q * d + k] = s * apk + c * aqk;
+        }
+      }
+  }
+  ev.resize(d);
+  for (int i = 0; i < d; ++i) ev[i] = A[i * d + i];
+}
+
+// Symmetric matrix from the moment sums of n items (slot layout of the moments pass):
+// (sum of products - sum_i sum_j / n) / denom.
+std::vector<double> scatter_matrix(const std::vector<double>& sums, int d, double n,
+                                   double denom, bool centre) {
+  std::vector<double> S((size_t)d * d);
+  int q = d;
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j <= i; ++j, ++q) {
+      const double c = (sums[q] - (centre ? sums[i] * sums[j] / n : 0.0)) / denom;
+      S[i * d + j] = S[j * d + i] = c;
+    }
+  return S;
+}
+
+int upload_whitening(best_ctx* h, const double* mu, const double* L, DevBuf& mu_d,
+                     DevBuf& L_d) {
+  if (!mu) return BEST_OK;
+  const int d = h->d;
+  if (!L) return fail(h, BEST_EINVAL, "whitening needs both mu and L");
+  for (int i = 0; i < d; ++i)
+    if (!(L[i * d + i] > 0) || !std::isfinite(L[i * d + i]))
+      return fail(h, BEST_EINVAL, "L must have a positive diagonal");
+  HIPCHK(h, mu_d.alloc((size_t)d * 8));
+  HIPCHK(h, L_d.alloc((size_t)d * d * 8));
+  HIPCHK(h, hipMemcpyAsync(mu_d.p, mu, (size_t)d * 8, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, hipMemcpyAsync(L_d.p, L, (size_t)d * d * 8, hipMemcpyHostToDevice, h->stream));
+  return BEST_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int best_rhat(best_ctx* h, const float* samples, int64_t T, int64_t n_chains, double* rminus1) {
+  if (!h) return BEST_EINVAL;
+  if (!samples || !rminus1 || T < 2 || n_chains < 2)
+    return fail(h, BEST_EINVAL, "samples/rminus1 NULL, T < 2 or n_chains < 2");
+  const int d = h->d, np = d + d * (d + 1) / 2, nblocks = 256;
+  const int64_t N = n_chains;
+  DevBuf mean, ssq, part, sums, shift0;
+  HIPCHK(h, mean.alloc((size_t)d * N * 8));
+  HIPCHK(h, ssq.alloc((size_t)d * N * 8));
+  HIPCHK(h, part.alloc((size_t)nblocks * np * 8));
+  HIPCHK(h, sums.alloc((size_t)np * 8));
+  HIPCHK(h, shift0.alloc((size_t)d * 8));
+  std::vector<double> sw(np), sb(np);
+  // chain means, then the within-chain scatter about each chain's own mean
+  HIPCHK(h, launch_ess_chain_stats(samples, T, d, N, mean.f64(), ssq.f64(), h->stream));
+  HIPCHK(h, launch_moment_sums(samples, nullptr, T, N, N, d, mean.f64(), N,
+                               part.f64(), nblocks, h->stream));
+  HIPCHK(h, launch_sum_parts(part.f64(), nblocks, np, sums.f64(), h->stream));
+  HIPCHK(h, hipMemcpyAsync(sw.data(), sums.p, (size_t)np * 8, hipMemcpyDeviceToHost, h->stream));
+  // scatter of the chain means about chain 0's mean
+  HIPCHK(h, hipMemcpy2DAsync(shift0.p, 8, mean.p, (size_t)N * 8, 8, d, hipMemcpyDeviceToDevice,
+                             h->stream));
+  HIPCHK(h, launch_moment_sums(nullptr, mean.f64(), 1, N, N, d, shift0.f64(), 0,
+                               part.f64(), nblocks, h->stream));
+  HIPCHK(h, launch_sum_parts(part.f64(), nblocks, np, sums.f64(), h->stream));
+  HIPCHK(h, hipMemcpyAsync(sb.data(), sums.p, (size_t)np * 8, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  // W = mean of the chain covariances, B = covariance of the chain means (both unbiased)
+  std::vector<double> W = scatter_matrix(sw, d, (double)(T * N), (double)N * (double)(T - 1), false);
+  std::vector<double> Bm = scatter_matrix(sb, d, (double)N, (double)(N - 1), true);
+  std::vector<double> dg(d);
+  for (int i = 0; i < d; ++i) {
+    dg[i] = std::sqrt(Bm[i * d + i]);
+    if (!(dg[i] > 0) || !std::isfinite(dg[i]))
+      return fail(h, BEST_EINVAL, "the chain means of a parameter are all equal (B_ii = 0)");
+  }
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j < d; ++j) {
+      W[i * d + j] /= dg[i] * dg[j];
+      Bm[i * d + j] /= dg[i] * dg[j];
+    }
+  // eigenvalues of W~^-1 B~ = those of G^-1 B~ G^-T with W~ = G G^T
+  std::vector<double> G((size_t)d * d, 0.0);
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j <= i; ++j) {
+      double s = W[i * d + j];
+      for (int k = 0; k < j; ++k) s -= G[i * d + k] * G[j * d + k];
+      if (i == j) {
+        if (!(s > 0) || !std::isfinite(s))
+          return fail(h, BEST_ENOTPD, "mean within-chain covariance is not positive definite");
+        G[i * d + i] = std::sqrt(s);
+      } else {
+        G[i * d + j] = s / G[j * d + j];
+      }
+    }
+  auto fsub = [&](std::vector<double>& M) {  // M <- G^-1 M, column by column
+    for (int c = 0; c < d; ++c)
+      for (int i = 0; i < d; ++i) {
+        double s = M[i * d + c];
+        for (int k = 0; k < i; ++k) s -= G[i * d + k] * M[k * d + c];
+        M[i * d + c] = s / G[i * d + i];
+      }
+  };
+  fsub(Bm);  // Y = G^-1 B~
+  std::vector<double> C((size_t)d * d);
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j < d; ++j) C[i * d + j] = Bm[j * d + i];  // Y^T = B~ G^-T
+  fsub(C);  // G^-1 B~ G^-T
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j < i; ++j) C[i * d + j] = C[j * d + i] = 0.5 * (C[i * d + j] + C[j * d + i]);
+  std::vector<double> ev;
+  sym_eigenvalues(C, d, ev);
+  double r = 0;
+  for (double v : ev) r = std::max(r, std::fabs(v));
+  *rminus1 = r;
+  return BEST_OK;
+}
+
+int best_credible(best_ctx* h, const float* samples, int64_t T, int64_t n_chains, double alpha,
+                  const double* mu, const double* L, const double* ref_lo, const double* ref_hi,
+                  double* lo, double* hi, double* metric) {
+  if (!h) return BEST_EINVAL;
+  if (!samples || T < 1 || n_chains < 1) return fail(h, BEST_EINVAL, "samples NULL or empty");
+  if (!(alpha > 0 && alpha < 1)) return fail(h, BEST_EINVAL, "alpha must be in (0, 1)");
+  if ((ref_lo == nullptr) != (ref_hi == nullptr) || (ref_lo && !metric))
+    return fail(h, BEST_EINVAL, "ref_lo, ref_hi and metric go together");
+  const int d = h->d;
+  const int64_t n = T * n_chains;
+  if (n >= ((int64_t)1 << 31)) return fail(h, BEST_EINVAL, "more than 2^31 - 1 draws");
+  int rc;
+  DevBuf mu_d, L_d, z, sorted, temp;
+  if ((rc = upload_whitening(h, mu, L, mu_d, L_d))) return rc;
+  HIPCHK(h, z.alloc((size_t)d * n * 8));
+  HIPCHK(h, sorted.alloc((size_t)n * 8));
+  HIPCHK(h, launch_whiten_points(samples, T, d, n_chains, mu_d.f64(), L_d.f64(),
+                                 z.f64(), n, h->stream));
+  size_t tb = 0;
+  HIPCHK(h, sort_keys_f64(nullptr, &tb, nullptr, nullptr, n, h->stream));
+  HIPCHK(h, temp.alloc(tb));
+  const double a = (1.0 - alpha) / 2.0;
+  const double lev[2] = {a, 1.0 - a};
+  std::vector<double> got((size_t)d * 4, 0.0);
+  std::vector<int64_t> kk(2);
+  for (int l = 0; l < 2; ++l) kk[l] = (int64_t)std::floor((double)(n - 1) * lev[l]);
+  for (int i = 0; i < d; ++i) {
+    size_t tbi = tb;
+    HIPCHK(h, sort_keys_f64(temp.p, &tbi, z.f64() + (size_t)i * n, sorted.f64(), n,
+                            h->stream));
+    for (int l = 0; l < 2; ++l) {
+      const int64_t k = std::min<int64_t>(kk[l], n - 1);
+      const int cnt = k + 1 < n ? 2 : 1;
+      HIPCHK(h, hipMemcpyAsync(&got[(size_t)i * 4 + 2 * l], sorted.f64() + k, cnt * 8,
+                               hipMemcpyDeviceToHost, h->stream));
+    }
+  }
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  double worst = 0;
+  for (int i = 0; i < d; ++i) {
+    double q[2];
+    for (int l = 0; l < 2; ++l) {
+      const double hh = (double)(n - 1) * lev[l];
+      const int64_t k = (int64_t)std::floor(hh);
+      const double v0 = got[(size_t)i * 4 + 2 * l], v1 = got[(size_t)i * 4 + 2 * l + 1];
+      q[l] = k >= n - 1 ? v0 : v0 + (hh - (double)k) * (v1 - v0);
+    }
+    if (lo) lo[i] = q[0];
+    if (hi) hi[i] = q[1];
+    if (ref_lo) {
+      const double dl = (std::fabs(q[1] - ref_hi[i]) + std::fabs(q[0] - ref_lo[i])) /
+                        (ref_hi[i] - ref_lo[i]);
+      worst = std::max(worst, dl);
+    }
+  }
+  if (ref_lo) *metric = worst;
+  return BEST_OK;
+}
+
+int best_sliced_wasserstein(best_ctx* h, const float* a, int64_t Ta, int64_t chains_a,
+                            const float* b, int64_t Tb, int64_t chains_b, int32_t n_proj,
+                            uint64_t proj_seed, const double* mu, const double* L, double* out) {
+  if (!h) return BEST_EINVAL;
+  if (!a || !b || !out || Ta < 1 || Tb < 1 || chains_a < 1 || chains_b < 1 || n_proj < 1)
+    return fail(h, BEST_EINVAL, "NULL argument, empty sample set or n_proj < 1");
+  const int d = h->d;
+  const int64_t na = Ta * chains_a, nb = Tb * chains_b, n = na + nb;
+  if (n >= ((int64_t)1 << 31)) return fail(h, BEST_EINVAL, "more than 2^31 - 1 draws");
+  const int P = std::min<int>(16, n_proj), nparts = 256;
+  int rc;
+  DevBuf mu_d, L_d, za, zb, w, keys, ks, lab, ls, scan, part, res, temp;
+  if ((rc = upload_whitening(h, mu, L, mu_d, L_d))) return rc;
+  HIPCHK(h, za.alloc((size_t)d * na * 8));
+  HIPCHK(h, zb.alloc((size_t)d * nb * 8));
+  HIPCHK(h, w.alloc((size_t)n_proj * d * 8));
+  HIPCHK(h, keys.alloc((size_t)P * n * 8));
+  HIPCHK(h, ks.alloc((size_t)n * 8));
+  HIPCHK(h, lab.alloc((size_t)n * 4));
+  HIPCHK(h, ls.alloc((size_t)n * 4));
+  HIPCHK(h, scan.alloc((size_t)n * 4));
+  HIPCHK(h, part.alloc((size_t)nparts * 8));
+  HIPCHK(h, res.alloc((size_t)n_proj * 8));
+  size_t tb = 0;
+  HIPCHK(h, sliced_w1_workspace(n, &tb));
+  HIPCHK(h, temp.alloc(tb));
+  HIPCHK(h, launch_whiten_points(a, Ta, d, chains_a, mu_d.f64(), L_d.f64(),
+                                 za.f64(), na, h->stream));
+  HIPCHK(h, launch_whiten_points(b, Tb, d, chains_b, mu_d.f64(), L_d.f64(),
+                                 zb.f64(), nb, h->stream));
+  const Rng rng{(uint32_t)(proj_seed & 0xFFFFFFFFu), (uint32_t)(proj_seed >> 32)};
+  HIPCHK(h, launch_directions(rng, d, n_proj, w.f64(), h->stream));
+  HIPCHK(h, hipMemsetD32Async((hipDeviceptr_t)lab.i32(), 0, (size_t)na, h->stream));
+  HIPCHK(h, hipMemsetD32Async((hipDeviceptr_t)(lab.i32() + na), 1, (size_t)nb, h->stream));
+  for (int k0 = 0; k0 < n_proj; k0 += P) {
+    const int pk = std::min(P, n_proj - k0);
+    const double* wk = w.f64() + (size_t)k0 * d;
+    HIPCHK(h, launch_project(za.f64(), d, na, na, wk, pk, keys.f64(), n, h->stream));
+    HIPCHK(h, launch_project(zb.f64(), d, nb, nb, wk, pk, keys.f64() + na, n,
+                             h->stream));
+    for (int p = 0; p < pk; ++p)
+      HIPCHK(h, sliced_w1_one(temp.p, tb, keys.f64() + (size_t)p * n, ks.f64(),
+                              lab.i32(), ls.i32(), scan.i32(), n, na, nb,
+                              part.f64(), nparts, res.f64() + k0 + p, h->stream));
+  }
+  std::vector<double> r(n_proj);
+  HIPCHK(h, hipMemcpyAsync(r.data(), res.p, (size_t)n_proj * 8, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  double s = 0;
+  for (double v : r) s += v;
+  *out = s / n_proj;
+  return BEST_OK;
+}
+
 
 }  // extern "C"
 
