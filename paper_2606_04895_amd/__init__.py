@@ -17,7 +17,8 @@ from ._abi import (BEST_AIES, BEST_BF16, BEST_FP16, BEST_FP32, BEST_FP64, BEST_H
 __all__ = ["BestError", "Ctx", "best_init", "best_logL_grad", "best_step", "best_adapt",
            "best_get_state", "best_set_state", "best_get_whitening", "best_set_whitening",
            "best_set_step_size", "best_get_step_counter", "best_set_step_counter",
-           "best_set_mlp", "best_ess", "best_mlp_nparams", "best_standardise",
+           "best_set_mlp", "best_ess", "best_rhat", "best_credible", "best_sliced_wasserstein",
+           "best_mlp_nparams", "best_standardise",
            "best_importance_weights", "Trainer", "EmulatorFn"]
 
 INITS = {"uniform": A.BEST_INIT_UNIFORM, "replicated": A.BEST_INIT_REPLICATED,
@@ -283,6 +284,52 @@ def best_ess(ctx, record, n=None):
     out = np.empty(ctx.d)
     ctx.check(_lib().best_ess(ctx.h, _tensor_ptr(record, "float32"), T, _dptr(out)))
     return out
+
+
+def _record(rec):
+    if rec.dim() != 3:
+        raise ValueError("expected a record [T][d][n_chains]")
+    return _tensor_ptr(rec, "float32"), int(rec.shape[0]), int(rec.shape[2])
+
+
+def _whitening(whitening):
+    if whitening is None:
+        return None, None
+    mu, L = whitening
+    return _f64(mu), _f64(L)
+
+
+def best_rhat(ctx, record):
+    """Multivariate R - 1 (Sec. 4.1) of a CUDA float32 record [T][d][n_chains]."""
+    p, T, n = _record(record)
+    out = np.empty(1)
+    ctx.check(_lib().best_rhat(ctx.h, p, T, n, _dptr(out)))
+    return float(out[0])
+
+
+def best_credible(ctx, record, alpha, whitening=None, ref=None):
+    """Equal-tailed credible limits at level alpha of every parameter, and with
+    ref = (lo0, hi0) the credible metric of Sec. 4.1.  whitening = (mu, L) or None.
+    Returns (lo, hi, metric or None)."""
+    p, T, n = _record(record)
+    mu, L = _whitening(whitening)
+    lo, hi = np.empty(ctx.d), np.empty(ctx.d)
+    r_lo, r_hi = (None, None) if ref is None else (_f64(ref[0]), _f64(ref[1]))
+    m = np.empty(1) if ref is not None else None
+    ctx.check(_lib().best_credible(ctx.h, p, T, n, float(alpha), _dptr(mu), _dptr(L),
+                                   _dptr(r_lo), _dptr(r_hi), _dptr(lo), _dptr(hi), _dptr(m)))
+    return lo, hi, (float(m[0]) if m is not None else None)
+
+
+def best_sliced_wasserstein(ctx, rec_a, rec_b, n_proj=500, proj_seed=0x5EED, whitening=None):
+    """Sliced Wasserstein distance (Sec. 4.1) between two CUDA float32 records."""
+    pa, Ta, na = _record(rec_a)
+    pb, Tb, nb = _record(rec_b)
+    mu, L = _whitening(whitening)
+    out = np.empty(1)
+    ctx.check(_lib().best_sliced_wasserstein(ctx.h, pa, Ta, na, pb, Tb, nb, int(n_proj),
+                                             int(proj_seed), _dptr(mu), _dptr(L), _dptr(out)))
+    return float(out[0])
 
 
 def best_standardise(y, stream=None):

@@ -92,6 +92,12 @@ EXPORTS = {
     "best_set_step_size": (C.c_int, [C.c_void_p, C.c_double]),
     "best_set_mlp": (C.c_int, [C.c_void_p, _dp, C.c_double, C.c_double]),
     "best_ess": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, _dp]),
+    "best_rhat": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, _dp]),
+    "best_credible": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_double, _dp,
+                                _dp, _dp, _dp, _dp, _dp, _dp]),
+    "best_sliced_wasserstein": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64,
+                                          C.c_void_p, C.c_int64, C.c_int64, C.c_int32,
+                                          C.c_uint64, _dp, _dp, _dp]),
     "best_trainer_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.c_int32, C.c_int32,
                                       _dp, C.c_int32, C.c_void_p]),
     "best_trainer_destroy": (None, [C.c_void_p]),

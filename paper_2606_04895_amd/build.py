@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libbest.so")
 SOURCES = ["kernels_bf16.hip", "kernels_f16.hip", "kernels_f32.hip", "kernels_f64.hip",
-           "kernels_aux.hip", "abi.cpp"]
+           "kernels_aux.hip", "metrics.hip", "abi.cpp"]
 ARCH = os.environ.get("BEST_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -28,6 +28,9 @@ hipError_t launch_aies_record(const State& S, int d, float* rec, int64_t slot, i
 hipError_t launch_moments(const float* rec, const double* xs, int64_t T, int64_t N,
                           int64_t pitch, int d, const double* shift, double* part, int nblocks,
                           int update_mean, double* mu, double* L, double* info, hipStream_t s);
+hipError_t launch_moment_sums(const float* rec, const double* xs, int64_t T, int64_t N,
+                              int64_t pitch, int d, const double* shift, int64_t spitch,
+                              double* part, int nblocks, hipStream_t s);
 hipError_t launch_ess_chain_stats(const float* rec, int64_t T, int d, int64_t N, double* mean,
                                   double* ssq, hipStream_t s);
 hipError_t launch_ess_autocov(const float* rec, const double* mean, int64_t T, int d,
@@ -42,5 +45,19 @@ hipError_t launch_standardise(const double* y, int64_t n, float* out, double* sc
                               double* stats_host, hipStream_t s);
 hipError_t launch_importance_weights(const double* lp, const double* le, int64_t n, double* w,
                                      double* scratch, double* stats_host, hipStream_t s);
+
+// metrics.hip (convergence metrics of Sec. 4.1)
+hipError_t launch_whiten_points(const float* rec, int64_t T, int d, int64_t N, const double* mu,
+                                const double* L, double* z, int64_t zpitch, hipStream_t s);
+hipError_t launch_sum_parts(const double* part, int nblocks, int np, double* out, hipStream_t s);
+hipError_t sort_keys_f64(void* temp, size_t* temp_bytes, const double* in, double* out,
+                         int64_t n, hipStream_t s);
+hipError_t launch_directions(const Rng& rng, int d, int K, double* w, hipStream_t s);
+hipError_t launch_project(const double* z, int d, int64_t n, int64_t zpitch, const double* w,
+                          int P, double* keys, int64_t kpitch, hipStream_t s);
+hipError_t sliced_w1_workspace(int64_t n, size_t* temp_bytes);
+hipError_t sliced_w1_one(void* temp, size_t temp_bytes, const double* keys, double* keys_sorted,
+                         const int* labels, int* labels_sorted, int* scan, int64_t n, int64_t na,
+                         int64_t nb, double* part, int nparts, double* out, hipStream_t s);
 
 }  // namespace best

@@ -143,7 +143,8 @@ enum Stream : uint32_t {
   kStreamAccept = 2,
   kStreamAies = 3,
   kStreamInit = 4,
-  kStreamNuts = 5
+  kStreamNuts = 5,
+  kStreamProj = 6
 };
 
 struct Rng {

@@ -115,10 +115,11 @@ __global__ void aies_record_kernel(State S, int d, float* rec, int64_t slot, int
 
 // ---- ensemble moments, pass 1: per-block shifted sums over items ----------------------
 // Items come from a float record [T][d][N] (item = t*N + c) or the FP64 state x [d][Np].
+// The shift is one vector s_i (spitch 0) or one per chain, s_i(c) = shift[i*spitch + c].
 // Slot p < d holds sum (v_i - s_i); slot d + pair(i, j), j <= i, holds sum of products.
 __global__ void moments_partial_kernel(const float* rec, const double* xs, int64_t T,
                                        int64_t N, int64_t pitch, int d, const double* shift,
-                                       double* part) {
+                                       int64_t spitch, double* part) {
   constexpr int kChunk = 128;
   __shared__ double v[kChunk][kMaxD + 1];
   const int np = d + d * (d + 1) / 2;
@@ -132,7 +133,7 @@ __global__ void moments_partial_kernel(const float* rec, const double* xs, int64
       const int64_t t = it / N, c = it % N;
       for (int i = 0; i < d; ++i) {
         const double x = rec ? (double)rec[(t * d + i) * pitch + c] : xs[i * pitch + c];
-        v[threadIdx.x][i] = x - shift[i];
+        v[threadIdx.x][i] = x - (spitch ? shift[i * spitch + c] : shift[i]);
       }
     }
     __syncthreads();
@@ -498,11 +499,19 @@ hipError_t launch_moments(const float* rec, const double* xs, int64_t T, int64_t
                           int64_t pitch, int d, const double* shift, double* part, int nblocks,
                           int update_mean, double* mu, double* L, double* info, hipStream_t s) {
   hipLaunchKernelGGL(moments_partial_kernel, dim3(nblocks), dim3(kAuxThreads), 0, s, rec, xs, T,
-                     N, pitch, d, shift, part);
+                     N, pitch, d, shift, (int64_t)0, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(moments_final_kernel, dim3(1), dim3(kAuxThreads), 0, s, part, nblocks,
                      T * N, d, shift, update_mean, mu, L, info);
+  return hipGetLastError();
+}
+
+hipError_t launch_moment_sums(const float* rec, const double* xs, int64_t T, int64_t N,
+                              int64_t pitch, int d, const double* shift, int64_t spitch,
+                              double* part, int nblocks, hipStream_t s) {
+  hipLaunchKernelGGL(moments_partial_kernel, dim3(nblocks), dim3(kAuxThreads), 0, s, rec, xs, T,
+                     N, pitch, d, shift, spitch, part);
   return hipGetLastError();
 }
 

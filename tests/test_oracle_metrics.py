@@ -4,28 +4,14 @@ brute-force optimal-transport linear program on tiny inputs, and invariances."""
 import numpy as np
 import pytest
 from scipy import optimize, stats
-from scipy.linalg import hadamard
 
 from oracle import metrics as OM
-
-
-def _walsh_chains(deltas, n_chains=8):
-    """Chains x_tc = m_c + y_t whose unbiased within-chain covariance is exactly I and whose
-    chain means are m_c = (delta_i s_i[c]) with orthogonal zero-mean sign vectors s_i, so
-    the unbiased covariance of the means is diag(delta_i^2 N / (N - 1))."""
-    d = len(deltas)
-    T = 2 * d
-    a = np.sqrt((T - 1) / 2.0)
-    y = np.concatenate([a * np.eye(d), -a * np.eye(d)])  # (T, d)
-    Hm = hadamard(n_chains)[:, 1:d + 1].astype(np.float64)  # columns orthogonal to ones
-    m = Hm * np.asarray(deltas)[None, :]  # (N, d)
-    rec = y[:, :, None] + m.T[None, :, :]  # (T, d, N)
-    return rec
+from workloads import walsh_chains
 
 
 def test_rhat_closed_form_from_sign_patterns():
     deltas = [0.3, 1.7, 0.9]
-    rec = _walsh_chains(deltas)
+    rec = walsh_chains(deltas)
     n = rec.shape[2]
     expect = max(dl * dl for dl in deltas) * n / (n - 1)
     assert OM.rhat_minus_one(rec) == pytest.approx(expect, rel=1e-12)

@@ -16,4 +16,5 @@ from .synth import (  # noqa: F401
     minibatch_permutations,
     ar1_chains,
     small_problem,
+    walsh_chains,
 )

@@ -276,3 +276,19 @@ def ar1_chains(rng: np.random.Generator, rho: float, n_chains: int, n_steps: int
     for t in range(1, n_steps):
         x[:, t] = rho * x[:, t - 1] + e[:, t]
     return x
+
+
+def walsh_chains(deltas, n_chains=8) -> np.ndarray:
+    """Record (T, d, N) of chains x_tc = m_c + y_t with T = 2d: the rows y_t = +-a e_k
+    (a^2 = (T - 1)/2) give every chain the unbiased covariance I exactly, and the chain means
+    m_c = (delta_i s_i[c]) use orthogonal zero-mean sign vectors s_i (Hadamard columns), so
+    the unbiased covariance of the means is diag(delta_i^2 N / (N - 1)).  n_chains is a
+    power of two above d."""
+    from scipy.linalg import hadamard
+    d = len(deltas)
+    T = 2 * d
+    a = np.sqrt((T - 1) / 2.0)
+    y = np.concatenate([a * np.eye(d), -a * np.eye(d)])
+    hm = hadamard(n_chains)[:, 1:d + 1].astype(np.float64)
+    m = hm * np.asarray(deltas, dtype=np.float64)[None, :]
+    return np.ascontiguousarray(y[:, :, None] + m.T[None, :, :])
