@@ -10,7 +10,8 @@ Counter layout used by every sampler (both implementations follow it independent
     c0 = chain index, c1 = step index (low 32 bits), c2 = (stream << 24) | substep,
     c3 = block index;  key = (seed low 32 bits, seed high 32 bits)
 Streams: 1 proposal / momentum normals, 2 accept uniform, 3 AIES partner + stretch,
-         4 walker initialisation, 5 NUTS tree decisions, 6 sliced-Wasserstein directions.
+         4 walker initialisation, 5 NUTS tree decisions, 6 sliced-Wasserstein directions,
+         7 differential-evolution partners and gamma noise.
 
 Uniform map: two 32-bit words (ra, rb) -> n = (ra >> 6) * 2^26 + (rb >> 6)  (52 bits)
              u = (n + 0.5) * 2^-52, exactly representable, strictly inside (0, 1).

@@ -23,6 +23,13 @@ AIES  (Sec. 2.3, stretch move):  the ensemble is split in halves S0 = [0, N/2), 
       z = ((a-1) u + 1)^2 / a;  y = x_j + z (x_k - x_j);
       log alpha = (d - 1) ln z + lp(y) - lp(x_k)   (Goodman & Weare 2010);
       S0 moves first against S1, then S1 against the updated S0.
+DE    (Sec. 2.3, differential-evolution move of the ensemble sampler): with the same two
+      half-ensembles, walker i takes two distinct partners j != k of the other half and
+      y = x_i + gamma (x_j - x_k),  gamma = (1 + eta) 2.38 / sqrt(2 d),  eta ~ N(0, s^2);
+      the proposal is symmetric (the pair (k, j) with the same gamma reverses it), so
+      log alpha = lp(y) - lp(x_i).  Philox stream 7, sub = half: block 0 gives the
+      partner uniforms (j from the first, k from the second among the other half's
+      walkers except j), block 1 the normal for eta (first member).
 """
 from __future__ import annotations
 
@@ -145,6 +152,47 @@ def aies_step(prob, st, t, seed, a=2.0, params=None):
         info["accept_prob"][act] = aprob
         info["partner"][act] = j
         info["z"][act] = zz
+    return dict(x=x, lp=lp), info
+
+
+STREAM_DE = 7
+DE_GAMMA0 = 2.38
+
+
+def de_step(prob, st, t, seed, sigma_gamma, params=None):
+    """One differential-evolution iteration of the ensemble (both halves, Sec. 2.3).
+    st = dict(x (N, d), lp (N,)); needs N even and N >= 4."""
+    x, lp = st["x"].copy(), st["lp"].copy()
+    n, d = x.shape
+    if n % 2 or n < 4:
+        raise ValueError("the DE move needs an even number of walkers >= 4")
+    half = n // 2
+    info = dict(accepted=np.zeros(n, bool), log_alpha=np.zeros(n), log_u=np.zeros(n),
+                accept_prob=np.zeros(n), partners=np.zeros((n, 2), np.int64),
+                gamma=np.zeros(n))
+    g0 = DE_GAMMA0 / np.sqrt(2.0 * d)
+    for h in (0, 1):
+        act = np.arange(h * half, (h + 1) * half)
+        comp0 = (1 - h) * half
+        ua, ub = ph.uniforms2(seed, act.astype(np.uint64), t, STREAM_DE, h, 0)
+        jj = np.minimum(np.floor(ua * half).astype(np.int64), half - 1)
+        kk = np.minimum(np.floor(ub * (half - 1)).astype(np.int64), half - 2)
+        kk = np.where(kk >= jj, kk + 1, kk)
+        eta = sigma_gamma * ph.normals(seed, act.astype(np.uint64), t, STREAM_DE, h, 3)[:, 2]
+        gamma = (1.0 + eta) * g0
+        y = x[act] + gamma[:, None] * (x[comp0 + jj] - x[comp0 + kk])
+        lpy, _ = log_target(prob, y, params)
+        log_alpha = lpy - lp[act]
+        log_u = np.log(ph.accept_uniform(seed, act.astype(np.uint64), t, sub=h))
+        acc, aprob = _accept(log_alpha, log_u)
+        x[act] = np.where(acc[:, None], y, x[act])
+        lp[act] = np.where(acc, lpy, lp[act])
+        info["accepted"][act] = acc
+        info["log_alpha"][act] = log_alpha
+        info["log_u"][act] = log_u
+        info["accept_prob"][act] = aprob
+        info["partners"][act] = np.stack([comp0 + jj, comp0 + kk], axis=1)
+        info["gamma"][act] = gamma
     return dict(x=x, lp=lp), info
 
 
