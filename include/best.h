@@ -65,6 +65,9 @@ extern "C" {
 #define BEST_NUTS 4 /* No-U-Turn sampler, Hoffman & Gelman's efficient slice version,
                        identity mass in whitened space (named among the samplers, Sec. 2.1) */
 #define BEST_NUTS_MAX_DEPTH 12
+#define BEST_DE 5   /* differential-evolution move of the ensemble sampler (Sec. 2.3):
+                       y = x_i + gamma (x_j - x_k), gamma = (1 + eta) 2.38 / sqrt(2 d),
+                       eta ~ N(0, de_sigma^2), two half-ensembles as for AIES */
 
 /* ---- walker initialisation (Sec. 3.2) ---- */
 #define BEST_INIT_UNIFORM 0    /* uniform in the prior box */
@@ -138,6 +141,7 @@ typedef struct {
   double target_accept;   /* dual-averaging target (e.g. 0.57 MALA, 0.8 HMC / NUTS) */
   int32_t max_depth;      /* NUTS maximum tree depth, 1 .. BEST_NUTS_MAX_DEPTH: at most
                              2^max_depth - 1 evaluations per transition */
+  double de_sigma;        /* DE: standard deviation of eta (>= 0; the paper's sigma_gamma) */
 } best_step_params;
 
 typedef struct {
@@ -192,7 +196,7 @@ int best_logL_grad(best_ctx *h, const double *x, int64_t n, double *logL, double
                    uint32_t flags);
 
 /* Advance every chain n_steps transitions of `sampler` (BEST_MH / MALA / HMC / AIES /
- * NUTS).  Randomness: Philox4x32-10 keyed by the seed, counter = (chain, global step,
+ * NUTS / DE).  AIES and DE need an even number of walkers (DE at least 4): BEST_ESTATE.  Randomness: Philox4x32-10 keyed by the seed, counter = (chain, global step,
  * stream << 24 | substep, block); the global step counter advances by n_steps.
  * out (may be NULL) receives the call's statistics; the call synchronises the stream.
  * MALA, HMC and NUTS need a gradient precision other than BEST_FP64 (BEST_ESTATE).  The

@@ -12,7 +12,8 @@ import numpy as np
 
 from . import _abi as A
 from ._abi import (BEST_AIES, BEST_BF16, BEST_FP16, BEST_FP32, BEST_FP64, BEST_HMC,  # noqa: F401
-                   BEST_MALA, BEST_MH, BEST_NUTS, BEST_NUTS_MAX_DEPTH, PRECISIONS, SAMPLERS)
+                   BEST_DE, BEST_MALA, BEST_MH, BEST_NUTS, BEST_NUTS_MAX_DEPTH, PRECISIONS,
+                   SAMPLERS)
 
 __all__ = ["BestError", "Ctx", "best_init", "best_logL_grad", "best_step", "best_adapt",
            "best_get_state", "best_set_state", "best_get_whitening", "best_set_whitening",
@@ -193,7 +194,8 @@ def best_logL_grad(ctx, x, want_grad=True, out=None):
 
 
 def best_step(ctx, sampler, n_steps, eps=0.0, mh_scale=0.0, stretch_a=2.0, n_leapfrog=10,
-              thin=1, record=None, adapt_eps=False, target_accept=0.57, max_depth=8):
+              thin=1, record=None, adapt_eps=False, target_accept=0.57, max_depth=8,
+              de_sigma=0.1):
     """Advance every chain n_steps transitions.  record: CUDA float32 tensor
     [capacity][d][n_chains] or None.  Returns the call's statistics as a dict."""
     lib = _lib()
@@ -206,6 +208,7 @@ def best_step(ctx, sampler, n_steps, eps=0.0, mh_scale=0.0, stretch_a=2.0, n_lea
     p.adapt_eps = int(bool(adapt_eps))
     p.target_accept = float(target_accept)
     p.max_depth = int(max_depth)
+    p.de_sigma = float(de_sigma)
     st = A.StepStats()
     s = SAMPLERS[sampler] if isinstance(sampler, str) else int(sampler)
     ctx.check(lib.best_step(ctx.h, s, int(n_steps), C.byref(p), C.byref(st)))

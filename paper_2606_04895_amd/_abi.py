@@ -9,14 +9,14 @@ LIB_PATH = os.path.join(HERE, "libbest.so")
 
 BEST_OK, BEST_EINVAL, BEST_ENOMEM, BEST_EHIP, BEST_ENOTPD, BEST_ESTATE = range(6)
 BEST_FP64, BEST_FP32, BEST_FP16, BEST_BF16 = range(4)
-BEST_MH, BEST_MALA, BEST_HMC, BEST_AIES, BEST_NUTS = range(5)
+BEST_MH, BEST_MALA, BEST_HMC, BEST_AIES, BEST_NUTS, BEST_DE = range(6)
 BEST_NUTS_MAX_DEPTH = 12
 BEST_INIT_UNIFORM, BEST_INIT_REPLICATED, BEST_INIT_GAUSSIAN = range(3)
 BEST_HOST_PTRS = 1
 
 PRECISIONS = {"fp64": BEST_FP64, "fp32": BEST_FP32, "fp16": BEST_FP16, "bf16": BEST_BF16}
 SAMPLERS = {"mh": BEST_MH, "mala": BEST_MALA, "hmc": BEST_HMC, "aies": BEST_AIES,
-            "nuts": BEST_NUTS}
+            "nuts": BEST_NUTS, "de": BEST_DE}
 
 _dp = C.POINTER(C.c_double)
 _fp = C.POINTER(C.c_float)
@@ -52,7 +52,8 @@ class StepParams(C.Structure):
     _fields_ = [("eps", C.c_double), ("mh_scale", C.c_double), ("stretch_a", C.c_double),
                 ("n_leapfrog", C.c_int32), ("thin", C.c_int32), ("record", _fp),
                 ("record_capacity", C.c_int64), ("adapt_eps", C.c_int32),
-                ("target_accept", C.c_double), ("max_depth", C.c_int32)]
+                ("target_accept", C.c_double), ("max_depth", C.c_int32),
+                ("de_sigma", C.c_double)]
 
 
 class StepStats(C.Structure):

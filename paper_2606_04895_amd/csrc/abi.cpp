@@ -597,7 +597,11 @@ int best_step(best_ctx* h, int32_t sampler, int64_t n_steps, const best_step_par
   if (!h) return BEST_EINVAL;
   int rc;
   if (!p) return fail(h, BEST_EINVAL, "params is NULL");
-  if (sampler < BEST_MH || sampler > BEST_NUTS) return fail(h, BEST_EINVAL, "unknown sampler");
+  if (sampler < BEST_MH || sampler > BEST_DE) return fail(h, BEST_EINVAL, "unknown sampler");
+  if (sampler == BEST_DE && !(p->de_sigma >= 0 && std::isfinite(p->de_sigma)))
+    return fail(h, BEST_EINVAL, "de_sigma must be finite and >= 0");
+  if (sampler == BEST_DE && (h->N < 4 || (h->N & 1)))
+    return fail(h, BEST_ESTATE, "the DE move needs an even number of walkers >= 4");
   if (sampler == BEST_NUTS && (p->max_depth < 1 || p->max_depth > BEST_NUTS_MAX_DEPTH))
     return fail(h, BEST_EINVAL, "max_depth must be in 1 .. BEST_NUTS_MAX_DEPTH");
   if (n_steps < 0) return fail(h, BEST_EINVAL, "n_steps < 0");
@@ -618,7 +622,8 @@ int best_step(best_ctx* h, int32_t sampler, int64_t n_steps, const best_step_par
                 "MALA/HMC/NUTS with FP64 GEMMs is switched off: an earlier build of this path "
                 "faulted on the GPU and the cause has not been shown yet");
   if (sampler == BEST_NUTS && (rc = ensure_nuts(h, p->max_depth))) return rc;
-  if (sampler != BEST_AIES && h->z_stale && (rc = rewhiten(h))) return rc;
+  const bool ensemble = sampler == BEST_AIES || sampler == BEST_DE;
+  if (!ensemble && h->z_stale && (rc = rewhiten(h))) return rc;
   if (gradient && h->gx_stale && (rc = refresh_state(h))) return rc;
   const size_t n1 = (size_t)h->Np;
   HIPCHK(h, hipMemsetAsync(h->st.n_acc, 0, n1 * 4, h->stream));
@@ -637,6 +642,7 @@ int best_step(best_ctx* h, int32_t sampler, int64_t n_steps, const best_step_par
   a.adapt = p->adapt_eps ? 1 : 0;
   a.mh_scale = p->mh_scale;
   a.stretch_a = p->stretch_a;
+  a.de_sigma = p->de_sigma;
   a.n_leap = p->n_leapfrog;
   a.thin = p->thin;
   a.record = p->record;
@@ -650,7 +656,7 @@ int best_step(best_ctx* h, int32_t sampler, int64_t n_steps, const best_step_par
   }
   const int64_t M = 16 * h->MT;
   const size_t lds = h->lds.total;
-  if (sampler == BEST_AIES) {
+  if (ensemble) {
     const int64_t half = h->N / 2;
     a.n_tiles = (half + M - 1) / M;
     const int grid = (int)std::min<int64_t>(a.n_tiles, h->grid_cap);
@@ -689,8 +695,8 @@ int best_step(best_ctx* h, int32_t sampler, int64_t n_steps, const best_step_par
   float ms = 0;
   HIPCHK(h, hipEventElapsedTime(&ms, h->ev0, h->ev1));
   h->step += (uint64_t)n_steps;
-  if (sampler == BEST_MH || sampler == BEST_AIES) h->gx_stale = true;
-  if (sampler == BEST_AIES) h->z_stale = true;
+  if (sampler == BEST_MH || ensemble) h->gx_stale = true;
+  if (ensemble) h->z_stale = true;
   if (out) {
     const int64_t per = sampler == BEST_HMC ? p->n_leapfrog : 1;
     out->accepted = si[0];

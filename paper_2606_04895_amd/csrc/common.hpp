@@ -144,7 +144,8 @@ enum Stream : uint32_t {
   kStreamAies = 3,
   kStreamInit = 4,
   kStreamNuts = 5,
-  kStreamProj = 6
+  kStreamProj = 6,
+  kStreamDE = 7
 };
 
 struct Rng {

@@ -1,5 +1,5 @@
 // Fused per-chain-tile kernels: target evaluation (FP64 assembly around the MLP emulator)
-// and the MH / MALA / HMC / AIES / NUTS transitions.  Templated on the GEMM precision P and the
+// and the MH / MALA / HMC / AIES / NUTS / differential-evolution transitions.  Templated on the GEMM precision P and the
 // chain-tile width M = 16*MT; instantiated once per precision in kernels_<prec>.hip.
 #pragma once
 #include "mlp_tile.hpp"
@@ -123,6 +123,7 @@ struct KArgs {
   double eps;
   const double* eps_ptr;
   double mh_scale, stretch_a;
+  double de_sigma;  // sd of eta in the differential-evolution gamma
   int n_leap;
   int thin;
   float* record;
@@ -936,6 +937,52 @@ __device__ __forceinline__ void nuts_tile(const KArgs& a, char* smem, typename P
   __syncthreads();
 }
 
+// Differential-evolution move: walker k of the active half [chain0, chain0 + half) moves
+// along the difference of two distinct walkers j != k' of the other half,
+// y = x_k + gamma (x_j - x_k'), gamma = (1 + eta) 2.38 / sqrt(2 d), eta ~ N(0, s^2); the
+// proposal is symmetric, so log alpha = log pi(y) - log pi(x_k).  Philox stream 7, sub =
+// half: block 0 holds the two partner uniforms, block 1 the normal for eta.
+template <class P, int MT>
+__device__ __forceinline__ void de_tile(const KArgs& a, char* smem, typename P::acc* hsave,
+                                        int64_t c0, int mv, uint64_t t) {
+  constexpr int M = 16 * MT;
+  const State& S = a.st;
+  const int d = a.tg.d, tid = local_tid();
+  const int64_t Np = S.Np, half = S.N / 2;
+  const int h = a.aies_half;
+  const int64_t other = (1 - h) * half;
+  const Scratch T = tile_scratch<MT>(a, smem, c0);
+  int* inbox = (int*)(smem + a.lds.mi);
+  int* flag = inbox + 2 * M;
+  const double g0 = 2.38 / sqrt(2.0 * (double)d);
+  for (int e = tid; e < d * M; e += kThreads) {
+    const int i = e / M, c = e % M;
+    if (c >= mv) continue;
+    const int64_t k = c0 + c;
+    const U4 b = a.rng.block(k, t, kStreamDE, (uint32_t)h, 0);
+    int64_t jj = (int64_t)floor(u52(b.x, b.y) * (double)half);
+    if (jj > half - 1) jj = half - 1;
+    int64_t kk = (int64_t)floor(u52(b.z, b.w) * (double)(half - 1));
+    if (kk > half - 2) kk = half - 2;
+    if (kk >= jj) kk += 1;
+    const double eta = a.de_sigma * normal_dim(a.rng, k, t, kStreamDE, (uint32_t)h, 2);
+    const double gam = (1.0 + eta) * g0;
+    T.xp(i, c) = S.x[i * Np + k] + gam * (S.x[i * Np + other + jj] - S.x[i * Np + other + kk]);
+  }
+  __syncthreads();
+  eval_tile<P, MT>(a, smem, hsave, T.xp, mv, T.lpp, T.gxp, false, true);
+  if (tid < mv) {
+    const int64_t k = c0 + tid;
+    const double lpp = T.lpp[tid];
+    const bool acc = decide(a, k, t, (uint32_t)h, lpp - S.lp[k], lpp, inbox[tid]);
+    flag[tid] = acc;
+    if (acc) S.lp[k] = lpp;
+  }
+  __syncthreads();
+  commit_tile(S, T, flag, d, M, mv, c0, false);
+  __syncthreads();
+}
+
 // Copy the launch's small constant arrays (whitening, Gaussian part, box, input scaling)
 // into LDS and point the kernel's argument copy at them; they are read in every phase of
 // every step.
@@ -985,7 +1032,8 @@ __global__ __launch_bounds__(kThreads, 1) void step_kernel(KArgs a) {
   stage_constants(a, smem);
   for (int64_t tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
     const int64_t c0 = a.chain0 + tile * M;
-    const int64_t lim = SAMPLER == 3 ? a.chain0 + a.st.N / 2 : a.st.N;
+    constexpr bool kHalves = SAMPLER == 3 || SAMPLER == 5;  // ensemble moves, one half per launch
+    const int64_t lim = kHalves ? a.chain0 + a.st.N / 2 : a.st.N;
     const int mv = (int)((lim - c0) < M ? (lim - c0) : M);
     for (int s = 0; s < a.n_steps; ++s) {
       const uint64_t t = (uint64_t)(a.step0 + s);
@@ -994,7 +1042,8 @@ __global__ __launch_bounds__(kThreads, 1) void step_kernel(KArgs a) {
       if constexpr (SAMPLER == 2) hmc_tile<P, MT>(a, smem, hsave, c0, mv, t, eps);
       if constexpr (SAMPLER == 3) aies_tile<P, MT>(a, smem, hsave, c0, mv, t);
       if constexpr (SAMPLER == 4) nuts_tile<P, MT>(a, smem, hsave, c0, mv, t, eps);
-      if constexpr (SAMPLER != 3) record_tile(a, s, a.tg.d, M, mv, c0);
+      if constexpr (SAMPLER == 5) de_tile<P, MT>(a, smem, hsave, c0, mv, t);
+      if constexpr (!kHalves) record_tile(a, s, a.tg.d, M, mv, c0);
     }
   }
 }

@@ -69,7 +69,7 @@ def burn_in(ctx, sampler, warmup, d, n, n_leap=10, mh_scale=None, stretch_a=2.0,
     kw = dict(n_leapfrog=n_leap, stretch_a=stretch_a, max_depth=max_depth,
               mh_scale=mh_scale if mh_scale else 2.4 / np.sqrt(d))
     t0 = time.perf_counter()
-    if sampler == "aies":
+    if sampler in ("aies", "de"):
         if warmup:
             best_step(ctx, sampler, warmup, **kw)
         return time.perf_counter() - t0

@@ -168,12 +168,13 @@ def test_training_reduces_loss_on_plain_model_pairs():
 
 @pytest.mark.parametrize("sampler,kw", [("mala", dict(eps=0.8)), ("hmc", dict(eps=0.5, n_leapfrog=5)),
                                         ("mh", dict(mh_scale=2.4 / np.sqrt(6))),
-                                        ("aies", dict(stretch_a=2.0))])
+                                        ("aies", dict(stretch_a=2.0)),
+                                        ("de", dict(de_sigma=0.1))])
 def test_gaussian_posterior_recovery(sampler, kw):
     prob = make_problem("c2", with_mlp=False)
     n = 4096
     ctx = _ctx_at_mean(prob, n)
-    steps = 300 if sampler != "aies" else 600
+    steps = 300 if sampler not in ("aies", "de") else 600
     B.best_step(ctx, sampler, 100, **kw)
     rec = torch.empty((steps, 6, n), dtype=torch.float32, device="cuda")
     B.best_step(ctx, sampler, steps, record=rec, **kw)

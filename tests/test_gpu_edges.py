@@ -111,6 +111,15 @@ def test_single_chain_lockstep(sampler, kw):
     _lockstep_tiny(prob, 1, sampler, kw, 0xBE58)
 
 
+def test_de_needs_four_walkers():
+    prob = small_problem(d=5, width=128, n_hidden=3)
+    ctx = B.best_init(prob, n_chains=2, precision="fp32", seed=3)
+    with pytest.raises(B.BestError) as e:
+        B.best_step(ctx, "de", 1, de_sigma=0.1)
+    assert e.value.code == 5
+    ctx.close()
+
+
 def test_two_walker_aies_lockstep():
     """The smallest AIES ensemble: each walker's only partner is the other one."""
     prob = small_problem(d=5, width=128, n_hidden=3, twist=True)

@@ -133,6 +133,10 @@ def _lockstep(prob, prec, sampler, n, steps=3, band=1e-6, state_tol=1e-4, **kw):
             lp0, _ = OT.log_target(prob, x0)
             new, info = OS.aies_step(prob, dict(x=x0, lp=lp0), t, seed, kw["stretch_a"])
             x_or = new["x"]
+        elif sampler == "de":
+            lp0, _ = OT.log_target(prob, x0)
+            new, info = OS.de_step(prob, dict(x=x0, lp=lp0), t, seed, kw["de_sigma"])
+            x_or = new["x"]
         else:
             fn = dict(mh=OS.mh_step, mala=OS.mala_step, hmc=OS.hmc_step)[sampler]
             args = dict(mh=(kw.get("mh_scale"),), mala=(kw.get("eps"),),
@@ -163,6 +167,7 @@ def _lockstep(prob, prec, sampler, n, steps=3, band=1e-6, state_tol=1e-4, **kw):
     ("mala", dict(eps=0.008)),
     ("hmc", dict(eps=0.07, n_leapfrog=5)),
     ("aies", dict(stretch_a=2.0)),
+    ("de", dict(de_sigma=0.2)),
 ])
 def test_lockstep_small(prec, sampler, kw):
     if prec == "fp64" and sampler in ("mala", "hmc"):
