@@ -14,6 +14,8 @@ MALA  (Sec. 2.1, the discretised Langevin proposal):
       z' = z + eps g(z) + sqrt(2 eps) xi,   proposal N(z + eps g(z), 2 eps I);
       log alpha = lp(z') - lp(z) + log q(z | z') - log q(z' | z),
       log q(a | b) = -|a - b - eps g(b)|^2 / (4 eps)
+      Per-dimension step multipliers (Sec. 4.3, larger steps for chosen whitened
+      dimensions): eps_i = eps m_i in the drift, the noise and q; MH scales xi_i by m_i.
 HMC   (Sec. 2.1 eq. hamiltonian with the identity mass of Sec. 2.2):
       q ~ N(0, I);  H = -lp(z) + |q|^2 / 2;  n_leap kick-drift-kick leapfrog steps;
       log alpha = H(start) - H(end).  Intermediate points use the unbounded density; only
@@ -50,12 +52,13 @@ def _chains(n, chains):
     return np.arange(n, dtype=np.uint64) if chains is None else np.asarray(chains, dtype=np.uint64)
 
 
-def mh_step(prob, W, st, t, seed, scale, chains=None, params=None):
+def mh_step(prob, W, st, t, seed, scale, chains=None, params=None, mult=None):
+    """mult: optional per-dimension step multipliers m (d,): z' = z + scale m xi."""
     z, lp = st["z"], st["lp"]
     n, d = z.shape
     ids = _chains(n, chains)
     xi = ph.normals(seed, ids, t, ph.STREAM_NORMAL, 0, d)
-    zp = z + scale * xi
+    zp = z + scale * xi if mult is None else z + (scale * np.asarray(mult))[None, :] * xi
     lpp, gp, _ = whitened(prob, W["mu"], W["L"], zp, params)
     log_alpha = lpp - lp
     log_u = np.log(ph.accept_uniform(seed, ids, t))
@@ -66,11 +69,27 @@ def mh_step(prob, W, st, t, seed, scale, chains=None, params=None):
                      proposal=zp)
 
 
-def mala_step(prob, W, st, t, seed, eps, chains=None, params=None):
+def mala_step(prob, W, st, t, seed, eps, chains=None, params=None, mult=None):
+    """mult: optional per-dimension step multipliers m (d,): dimension i uses the step
+    eps m_i in the drift, the noise sqrt(2 eps m_i) and its proposal density."""
     z, lp, g = st["z"], st["lp"], st["g"]
     n, d = z.shape
     ids = _chains(n, chains)
     xi = ph.normals(seed, ids, t, ph.STREAM_NORMAL, 0, d)
+    if mult is not None:
+        e = eps * np.asarray(mult, dtype=np.float64)[None, :]
+        zp = z + e * g + np.sqrt(2.0 * e) * xi
+        lpp, gp, _ = whitened(prob, W["mu"], W["L"], zp, params)
+        with np.errstate(invalid="ignore"):
+            log_q_rev = -np.sum((z - zp - e * gp) ** 2 / (4.0 * e), axis=1)
+            log_q_fwd = -np.sum((zp - z - e * g) ** 2 / (4.0 * e), axis=1)
+            log_alpha = lpp - lp + log_q_rev - log_q_fwd
+        log_u = np.log(ph.accept_uniform(seed, ids, t))
+        acc, aprob = _accept(log_alpha, log_u)
+        new = dict(z=np.where(acc[:, None], zp, z), lp=np.where(acc, lpp, lp),
+                   g=np.where(acc[:, None], gp, g))
+        return new, dict(accepted=acc, log_alpha=log_alpha, log_u=log_u, accept_prob=aprob,
+                         proposal=zp)
     zp = z + eps * g + np.sqrt(2.0 * eps) * xi
     lpp, gp, _ = whitened(prob, W["mu"], W["L"], zp, params)
     with np.errstate(invalid="ignore"):
