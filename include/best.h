@@ -223,6 +223,11 @@ int best_set_whitening(best_ctx *h, const double *mu, const double *L);
 uint64_t best_get_step_counter(const best_ctx *h);
 int best_set_step_counter(best_ctx *h, uint64_t step);
 int best_set_step_size(best_ctx *h, double eps);
+/* Per-dimension step multipliers m (host [d], each finite and > 0; NULL removes them) for
+ * the whitened-space MALA and MH transitions (Sec. 4.3: larger steps for chosen
+ * dimensions): dimension i uses eps m_i in MALA's drift, noise and proposal density, and
+ * mh_scale m_i in MH.  HMC and NUTS ignore them.  Kept until replaced. */
+int best_set_step_multipliers(best_ctx *h, const double *m);
 /* Replace the MLP weights (flat host vector, same layout as best_problem.mlp_params). */
 int best_set_mlp(best_ctx *h, const double *params, double mlp_coef, double offset);
 

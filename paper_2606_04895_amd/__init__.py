@@ -17,7 +17,8 @@ from ._abi import (BEST_AIES, BEST_BF16, BEST_FP16, BEST_FP32, BEST_FP64, BEST_H
 
 __all__ = ["BestError", "Ctx", "best_init", "best_logL_grad", "best_step", "best_adapt",
            "best_get_state", "best_set_state", "best_get_whitening", "best_set_whitening",
-           "best_set_step_size", "best_get_step_counter", "best_set_step_counter",
+           "best_set_step_size", "best_set_step_multipliers", "best_get_step_counter",
+           "best_set_step_counter",
            "best_set_mlp", "best_ess", "best_rhat", "best_credible", "best_sliced_wasserstein",
            "best_mlp_nparams", "best_standardise",
            "best_importance_weights", "Trainer", "EmulatorFn"]
@@ -274,6 +275,12 @@ def best_get_step_counter(ctx):
 
 def best_set_step_counter(ctx, step):
     ctx.check(_lib().best_set_step_counter(ctx.h, int(step)))
+
+
+def best_set_step_multipliers(ctx, m):
+    """Per-dimension step multipliers (host [d]) for MALA and MH; None removes them."""
+    ma = _f64(m)
+    ctx.check(_lib().best_set_step_multipliers(ctx.h, _dptr(ma)))
 
 
 def best_set_mlp(ctx, params, mlp_coef, offset=0.0):

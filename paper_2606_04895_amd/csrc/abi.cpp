@@ -171,6 +171,8 @@ struct best_ctx {
   int64_t es_cap = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   double* nu_buf = nullptr;  // NUTS trajectory buffers (allocated by the first NUTS call)
+  double* mult = nullptr;    // per-dimension step multipliers [d] (MALA, MH)
+  bool mult_on = false;
   NutsState nu{};
   std::vector<double> lower, upper;
   double mlp_coef = 0, offset = 0;
@@ -643,6 +645,7 @@ int best_step(best_ctx* h, int32_t sampler, int64_t n_steps, const best_step_par
   a.mh_scale = p->mh_scale;
   a.stretch_a = p->stretch_a;
   a.de_sigma = p->de_sigma;
+  a.step_mult = h->mult_on ? h->mult : nullptr;
   a.n_leap = p->n_leapfrog;
   a.thin = p->thin;
   a.record = p->record;
@@ -829,6 +832,23 @@ int best_set_step_size(best_ctx* h, double eps) {
   da[0] = std::log(10.0 * eps);
   da[1] = da[2] = da[3] = 0;
   HIPCHK(h, hipMemcpy(h->da, da, sizeof(da), hipMemcpyHostToDevice));
+  return BEST_OK;
+}
+
+int best_set_step_multipliers(best_ctx* h, const double* m) {
+  if (!h) return BEST_EINVAL;
+  if (!m) {
+    h->mult_on = false;
+    return BEST_OK;
+  }
+  for (int i = 0; i < h->d; ++i)
+    if (!(m[i] > 0) || !std::isfinite(m[i]))
+      return fail(h, BEST_EINVAL, "step multipliers must be finite and > 0");
+  if (!h->mult && h->mem.alloc(&h->mult, (size_t)h->d) != hipSuccess)
+    return fail(h, BEST_ENOMEM, "step multipliers");
+  HIPCHK(h, hipMemcpyAsync(h->mult, m, (size_t)h->d * 8, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  h->mult_on = true;
   return BEST_OK;
 }
 

@@ -124,6 +124,7 @@ struct KArgs {
   const double* eps_ptr;
   double mh_scale, stretch_a;
   double de_sigma;  // sd of eta in the differential-evolution gamma
+  const double* step_mult;  // per-dimension step multipliers [d] (MALA, MH) or nullptr
   int n_leap;
   int thin;
   float* record;
@@ -515,7 +516,8 @@ __device__ __forceinline__ void mh_tile(const KArgs& a, char* smem, typename P::
   for (int e = tid; e < d * M; e += kThreads) {
     const int i = e / M, c = e % M;
     if (c >= mv) continue;
-    T.zp(i, c) = T.z(i, c) + a.mh_scale * normal_dim(a.rng, c0 + c, t, kStreamNormal, 0, i);
+    const double s = a.step_mult ? a.mh_scale * a.step_mult[i] : a.mh_scale;
+    T.zp(i, c) = T.z(i, c) + s * normal_dim(a.rng, c0 + c, t, kStreamNormal, 0, i);
   }
   __syncthreads();
   tile_affine(a.wh.mu, a.wh.L, d, M, mv, T.zp, T.xp);
@@ -545,14 +547,16 @@ __device__ __forceinline__ void mala_tile(const KArgs& a, char* smem, typename P
   const TView GX{S.gx + c0, S.Np};
   int* inbox = (int*)(smem + a.lds.mi);
   int* flag = inbox + 2 * M;
+  const double* mult = a.step_mult;  // per-dimension steps eps_i = eps m_i when set
   const double sq = sqrt(2.0 * eps);
   tile_whiten(a.wh.mu, Lw, d, mv, TView{S.x + c0, S.Np}, T.z);
   for (int e = tid; e < d * M; e += kThreads) {
     const int i = e / M, c = e % M;
     if (c >= mv) continue;
     const double gzi = lt_dot(Lw, d, i, GX, c);
+    const double ei = mult ? eps * mult[i] : eps, sqi = mult ? sqrt(2.0 * ei) : sq;
     T.gz(i, c) = gzi;
-    T.zp(i, c) = T.z(i, c) + eps * gzi + sq * normal_dim(a.rng, c0 + c, t, kStreamNormal, 0, i);
+    T.zp(i, c) = T.z(i, c) + ei * gzi + sqi * normal_dim(a.rng, c0 + c, t, kStreamNormal, 0, i);
   }
   __syncthreads();
   tile_affine(a.wh.mu, Lw, d, M, mv, T.zp, T.xp);
@@ -568,14 +572,26 @@ __device__ __forceinline__ void mala_tile(const KArgs& a, char* smem, typename P
     const int c = tid;
     const int64_t ch = c0 + c;
     double fwd = 0, rev = 0;
-    for (int i = 0; i < d; ++i) {
-      const double df = T.zp(i, c) - T.z(i, c) - eps * T.gz(i, c);
-      const double dr = T.z(i, c) - T.zp(i, c) - eps * T.gzp(i, c);
-      fwd += df * df;
-      rev += dr * dr;
+    if (mult) {  // sums of the per-dimension terms |.|^2 / (4 eps_i)
+      for (int i = 0; i < d; ++i) {
+        const double ei = eps * mult[i];
+        const double df = T.zp(i, c) - T.z(i, c) - ei * T.gz(i, c);
+        const double dr = T.z(i, c) - T.zp(i, c) - ei * T.gzp(i, c);
+        fwd += df * df / (4.0 * ei);
+        rev += dr * dr / (4.0 * ei);
+      }
+    } else {
+      for (int i = 0; i < d; ++i) {
+        const double df = T.zp(i, c) - T.z(i, c) - eps * T.gz(i, c);
+        const double dr = T.z(i, c) - T.zp(i, c) - eps * T.gzp(i, c);
+        fwd += df * df;
+        rev += dr * dr;
+      }
+      fwd /= 4.0 * eps;
+      rev /= 4.0 * eps;
     }
     const double lpp = T.lpp[c];
-    const double la = lpp - S.lp[ch] + (-rev / (4.0 * eps)) - (-fwd / (4.0 * eps));
+    const double la = lpp - S.lp[ch] + (-rev) - (-fwd);
     const bool acc = decide(a, ch, t, 0, la, lpp, inbox[c]);
     flag[c] = acc;
     if (acc) S.lp[ch] = lpp;

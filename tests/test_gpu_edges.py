@@ -124,3 +124,39 @@ def test_two_walker_aies_lockstep():
     """The smallest AIES ensemble: each walker's only partner is the other one."""
     prob = small_problem(d=5, width=128, n_hidden=3, twist=True)
     _lockstep_tiny(prob, 2, "aies", dict(stretch_a=2.0), 0xBE59)
+
+
+@pytest.mark.parametrize("sampler,kw,arg", [("mala", dict(eps=0.008), 0.008),
+                                            ("mh", dict(mh_scale=0.3), 0.3)])
+def test_step_multipliers_lockstep(sampler, kw, arg):
+    """Per-dimension steps (MALA eps m_i, MH scale m_i) against the oracle; removing the
+    multipliers restores the plain transition."""
+    prob = small_problem(d=5, width=128, n_hidden=3, twist=True)
+    m = np.array([3.0, 2.0, 1.0, 0.5, 0.25])  # smaller steps on the narrow twisted pair
+    seed = 0xBE5A
+    ctx = B.best_init(prob, n_chains=70, precision="fp32", seed=seed, init="gaussian",
+                      init_point=prob["gauss_mean"], init_scale=0.05)
+    B.best_set_whitening(ctx, prob["gauss_mean"], np.linalg.cholesky(prob["closed_cov"]))
+    fn = OS.mala_step if sampler == "mala" else OS.mh_step
+    for s in range(4):
+        use = m if s < 3 else None
+        B.best_set_step_multipliers(ctx, use)
+        t = B.best_get_step_counter(ctx)
+        x0 = B.best_get_state(ctx)[0].T.copy()
+        mu, L = B.best_get_whitening(ctx)
+        W = dict(mu=mu, L=L)
+        new, info = fn(prob, W, OS.init_state(prob, W, x0), t, seed, arg, mult=use)
+        x_or = W["mu"][None, :] + new["z"] @ W["L"].T
+        B.best_step(ctx, sampler, 1, **kw)
+        x1 = B.best_get_state(ctx)[0].T
+        bad = np.any(x1 != x0, axis=1) != info["accepted"]
+        if bad.any():
+            assert np.all(np.abs(info["log_alpha"] - info["log_u"])[bad] < 1e-6)
+        ok = ~bad
+        scale = np.abs(x_or[ok]) + np.abs(x_or[ok] - x0[ok]) + 1e-12
+        assert np.all(np.abs(x1[ok] - x_or[ok]) / scale < 1e-4)
+        assert 0 < info["accepted"].mean()
+    with pytest.raises(B.BestError) as e:
+        B.best_set_step_multipliers(ctx, np.array([1.0, 0.0, 1.0, 1.0, 1.0]))
+    assert e.value.code == 1
+    ctx.close()
