@@ -21,7 +21,8 @@ Hoffman & Gelman's efficient algorithm in the whitened space of Sec. 2.2 (identi
 Readings where the algorithm leaves a choice (also used by the HIP path):
   * the prior box: a leaf outside it has log pi = -inf (never a valid point, and it stops
     the trajectory as a divergence); the leapfrog dynamics use the unbounded density, as
-    in the HMC transition;
+    in the HMC transition; with the smooth box penalty the penalised density is used
+    everywhere;
   * the acceptance statistic for step-size adaptation is the mean over every leaf of the
     transition of min(1, exp(H(z0, q0) - H(leaf)));
   * random numbers (Philox counters, step t):
@@ -40,7 +41,7 @@ from __future__ import annotations
 import numpy as np
 
 from . import philox as ph
-from .target import whitened
+from .target import hard_box, whitened
 
 STREAM_NUTS = 5
 DELTA_MAX = 1000.0
@@ -86,7 +87,8 @@ def nuts_step(prob, W, st, t, seed, eps, max_depth=8, chains=None, params=None):
             qh = leaf.q + 0.5 * v * eps * leaf.g
             z = leaf.z + v * eps * qh
             lpu, g, x = whitened(prob, mu, L, z[None, :], params, with_box=False)
-            inside = bool(np.all((x[0] >= prob["lower"]) & (x[0] <= prob["upper"])))
+            inside = bool(np.all((x[0] >= prob["lower"]) & (x[0] <= prob["upper"]))) or \
+                not hard_box(prob)
             q = qh + 0.5 * v * eps * g[0]
             return _Leaf(z, q, g[0], float(lpu[0]) if inside else -np.inf)
 

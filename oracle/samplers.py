@@ -38,7 +38,7 @@ from __future__ import annotations
 import numpy as np
 
 from . import philox as ph
-from .target import whitened, log_target
+from .target import hard_box, whitened, log_target
 
 
 def _accept(log_alpha, log_u):
@@ -125,7 +125,8 @@ def hmc_step(prob, W, st, t, seed, eps, n_leap, chains=None, params=None):
     z1, q1, lp1, g1 = leapfrog(prob, W, z0, q0, g0, eps, n_leap, params)
     x1 = W["mu"][None, :] + z1 @ W["L"].T
     inside = np.all((x1 >= prob["lower"]) & (x1 <= prob["upper"]), axis=1)
-    lp1 = np.where(inside, lp1, -np.inf)
+    if hard_box(prob):
+        lp1 = np.where(inside, lp1, -np.inf)
     h1 = -lp1 + 0.5 * np.sum(q1 * q1, axis=1)
     with np.errstate(invalid="ignore"):
         log_alpha = h0 - h1

@@ -5,6 +5,10 @@ log pi(x) for the declarative targets sampled here:
   inside the prior box [lower, upper] (Sec. 3.1 bounds; a hard box, i.e. a uniform prior):
       gauss_coef * G(phi(x))  +  part(x)  + offset
   outside: -inf (the gradient returned there is that of the unbounded expression)
+  or, with box_penalty = 1, the smooth penalty of Sec. 3.1 instead of -inf:
+      - sum_i [exp(r_i / w) - 1 - r_i / w],  r_i = (distance of x_i outside [l_i, u_i]) /
+      (u_i - l_i), w = penalty_width: zero with zero slope at the faces (the density stays
+      differentiable) and growing exponentially outside.
 
   G(y)    = -1/2 (y - m)^T P (y - m)                      (Gaussian part, precision P)
   phi(x)  = x except phi_v = x_v + beta((x_u - c)^2 - kappa) (twisted "banana" pair, unit
@@ -94,6 +98,24 @@ def mlp_part(prob, x, params=None):
     return prob["mlp_coef"] * out, prob["mlp_coef"] * gth * prob["in_invscale"]
 
 
+def hard_box(prob):
+    """True when the prior box is hard (-inf outside), False with the smooth penalty."""
+    return not prob.get("box_penalty", 0)
+
+
+def box_penalty(prob, x):
+    """The smooth boundary penalty P(x) >= 0 and its gradient (n, d)."""
+    lo, hi = prob["lower"], prob["upper"]
+    width = hi - lo
+    w = float(prob.get("penalty_width", 0.01))
+    over = np.maximum(x - hi, 0.0) / width
+    under = np.maximum(lo - x, 0.0) / width
+    r = over + under
+    p = np.sum(np.expm1(r / w) - r / w, axis=1)
+    dr = np.where(over > 0, 1.0, np.where(under > 0, -1.0, 0.0)) / width
+    return p, (np.expm1(r / w) / w) * dr
+
+
 def log_target(prob, x, params=None, with_box=True):
     """log pi(x) and grad_x log pi(x) for a batch x (n, d)."""
     x = np.atleast_2d(np.asarray(x, dtype=np.float64))
@@ -122,7 +144,11 @@ def log_target(prob, x, params=None, with_box=True):
             pv, pg = plain_logL(prob["plain"], x[~inside])
             lp[~inside] += pv
             g[~inside] += pg
-    if with_box:
+    if not hard_box(prob):
+        pv, pg = box_penalty(prob, x)
+        lp -= pv
+        g -= pg
+    elif with_box:
         lp = np.where(in_box(prob["lower"], prob["upper"], x), lp, -np.inf)
     return lp, g
 
