@@ -114,6 +114,10 @@ typedef struct {
   int32_t plain_mode; /* 0, 1 or 2 (see top) */
   const double *train_lo, *train_hi; /* [d], plain_mode 1 only */
   const best_plain_model *plain;     /* plain_mode 1 or 2 */
+  int32_t box_penalty;  /* 0: hard box (log pi = -inf outside); 1: smooth penalty (Sec. 3.1)
+                           - sum_i [exp(r_i/w) - 1 - r_i/w] outside, r_i = distance outside
+                           the box in box widths, zero value and slope at the faces */
+  double penalty_width; /* w of the penalty (> 0, e.g. 0.01); ignored for the hard box */
 } best_problem;
 
 typedef struct {
@@ -150,7 +154,7 @@ typedef struct {
                               every chain's trajectory (the idle slots of chains that
                               stopped before others in their tile are not counted) */
   int64_t n_nonfinite;     /* proposals whose log pi was NaN (rejected) */
-  int64_t n_oob;           /* proposals outside the prior box (rejected) */
+  int64_t n_oob;           /* proposals outside the prior box (rejected with the hard box) */
   int64_t n_recorded;      /* record slots written */
   double sum_accept_prob;  /* sum of min(1, alpha); NUTS: of the per-transition mean over
                               leaves of min(1, exp(H0 - H)) */
@@ -190,8 +194,8 @@ int64_t best_mlp_nparams(int32_t d, int32_t width, int32_t n_hidden);
 
 /* Batch evaluation of log pi(x) and grad_x log pi(x) at n points x ([d][n]).  grad may be
  * NULL (logL only).  Device pointers, or host pointers with BEST_HOST_PTRS (then the call
- * synchronises).  The prior box applies (-inf outside; the gradient returned there is that
- * of the unbounded expression). */
+ * synchronises).  The prior box applies: -inf outside (the gradient returned there is that
+ * of the unbounded expression), or the smooth penalty with box_penalty = 1. */
 int best_logL_grad(best_ctx *h, const double *x, int64_t n, double *logL, double *grad,
                    uint32_t flags);
 

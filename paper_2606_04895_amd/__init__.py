@@ -129,6 +129,8 @@ def _problem_struct(prob):
     ps.in_center, ps.in_invscale = arr(prob.get("in_center")), arr(prob.get("in_invscale"))
     ps.mlp_coef, ps.offset = float(prob.get("mlp_coef", 0.0)), float(prob.get("offset", 0.0))
     ps.plain_mode = int(prob.get("plain_mode", 0))
+    ps.box_penalty = int(prob.get("box_penalty", 0))
+    ps.penalty_width = float(prob.get("penalty_width", 0.01))
     ps.train_lo, ps.train_hi = arr(prob.get("train_lo")), arr(prob.get("train_hi"))
     pl = prob.get("plain")
     if pl is not None and ps.plain_mode != 0:

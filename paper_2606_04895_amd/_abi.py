@@ -39,7 +39,8 @@ class Problem(C.Structure):
                 ("in_center", _dp), ("in_invscale", _dp),
                 ("mlp_coef", C.c_double), ("offset", C.c_double),
                 ("plain_mode", C.c_int32), ("train_lo", _dp), ("train_hi", _dp),
-                ("plain", C.POINTER(PlainModel))]
+                ("plain", C.POINTER(PlainModel)),
+                ("box_penalty", C.c_int32), ("penalty_width", C.c_double)]
 
 
 class Config(C.Structure):

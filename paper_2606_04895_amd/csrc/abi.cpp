@@ -294,6 +294,9 @@ static int validate_problem(best_ctx* h, const best_problem* p, const best_confi
       (p->twist_u >= d || p->twist_v < 0 || p->twist_v >= d || p->twist_u == p->twist_v))
     return fail(h, BEST_EINVAL, "twist indices out of range");
   if (p->plain_mode < 0 || p->plain_mode > 2) return fail(h, BEST_EINVAL, "plain_mode must be 0, 1 or 2");
+  if (p->box_penalty < 0 || p->box_penalty > 1) return fail(h, BEST_EINVAL, "box_penalty must be 0 or 1");
+  if (p->box_penalty && !(p->penalty_width > 0 && std::isfinite(p->penalty_width)))
+    return fail(h, BEST_EINVAL, "penalty_width must be finite and > 0");
   if (p->plain_mode != 2 && (!p->mlp_params || !p->in_center || !p->in_invscale))
     return fail(h, BEST_EINVAL, "MLP parameters or input normalisation is NULL");
   if (p->plain_mode != 0) {
@@ -375,6 +378,8 @@ static int upload_problem(best_ctx* h, const best_problem* p) {
   h->mlp_coef = p->mlp_coef;
   h->offset = p->offset;
   t.plain_mode = p->plain_mode;
+  t.box_penalty = p->box_penalty;
+  t.pen_w = p->box_penalty ? p->penalty_width : 1.0;
   HIPCHK(h, m.upload((double**)&t.train_lo, p->train_lo ? p->train_lo : p->lower, d, s));
   HIPCHK(h, m.upload((double**)&t.train_hi, p->train_hi ? p->train_hi : p->upper, d, s));
   if (p->plain_mode != 0) {

@@ -21,7 +21,26 @@ struct Target {
   const double *train_lo, *train_hi;
   int n_bins, n_terms;
   const double *xgrid, *data, *w2, *pa, *pg, *pp, *pk, *pg0, *pc, *pis;
+  int box_penalty;  // 1: smooth penalty outside the prior box instead of -inf
+  double pen_w;     // its width w (in box widths)
 };
+
+// Smooth boundary penalty: r = distance of x_i outside [lower_i, upper_i] in box widths,
+// P_i = exp(r/w) - 1 - r/w (zero value and slope at the face), dP_i/dx_i returned in *dp.
+__device__ __forceinline__ double box_pen(const Target& tg, int i, double x, double* dp) {
+  const double wd = tg.upper[i] - tg.lower[i];
+  double r = 0.0, s = 0.0;
+  if (x > tg.upper[i]) {
+    r = (x - tg.upper[i]) / wd;
+    s = 1.0 / wd;
+  } else if (x < tg.lower[i]) {
+    r = (tg.lower[i] - x) / wd;
+    s = -1.0 / wd;
+  }
+  const double em = expm1(r / tg.pen_w);
+  *dp = em / tg.pen_w * s;
+  return em - r / tg.pen_w;
+}
 
 struct Whiten {
   const double* mu;  // [d]
@@ -351,7 +370,14 @@ __device__ __forceinline__ void eval_tile(const KArgs& a, char* smem, typename P
     }
     const bool use_mlp = tg.plain_mode == 0 || (tg.plain_mode == 1 && intrain[c]);
     lp += use_mlp ? tg.mlp_coef * (double)s.out[c] : pv[c];
-    if (box && !inbox[c]) lp = -INFINITY;
+    if (tg.box_penalty) {
+      if (!inbox[c]) {
+        double dp;
+        for (int i = 0; i < d; ++i) lp -= box_pen(tg, i, X(i, c), &dp);
+      }
+    } else if (box && !inbox[c]) {
+      lp = -INFINITY;
+    }
     LPo[c] = lp;
   }
   if (grad) {
@@ -369,6 +395,11 @@ __device__ __forceinline__ void eval_tile(const KArgs& a, char* smem, typename P
       }
       const bool use_mlp = tg.plain_mode == 0 || (tg.plain_mode == 1 && intrain[c]);
       gi += use_mlp ? tg.mlp_coef * (double)s.gth[c * d + i] * tg.in_invscale[i] : pgr[c * d + i];
+      if (tg.box_penalty && !inbox[c]) {
+        double dp;
+        box_pen(tg, i, X(i, c), &dp);
+        gi -= dp;
+      }
       GXo(i, c) = gi;
     }
   }
@@ -655,7 +686,7 @@ __device__ __forceinline__ void hmc_tile(const KArgs& a, char* smem, typename P:
     const int64_t ch = c0 + tid;
     double k = 0;
     for (int i = 0; i < d; ++i) k += T.q(i, tid) * T.q(i, tid);
-    const double lp1 = inbox[tid] ? T.lpp[tid] : -INFINITY;
+    const double lp1 = (inbox[tid] || a.tg.box_penalty) ? T.lpp[tid] : -INFINITY;
     const double h1 = -lp1 + 0.5 * k;
     const double la = h0[tid] - h1;
     const bool acc = decide(a, ch, t, 0, la, lp1, inbox[tid]);
@@ -851,7 +882,7 @@ __device__ __forceinline__ void nuts_tile(const KArgs& a, char* smem, typename P
         }
         const double kin = group_sum(q * q, dp);
         const int ib = inbox[c];
-        const double lp = ib ? T.lpp[c] : -INFINITY;
+        const double lp = (ib || a.tg.box_penalty) ? T.lpp[c] : -INFINITY;
         const double h = -lp + 0.5 * kin;
         const double ls = lslice[c];
         bool go = ls < -h + kNutsDeltaMax;
