@@ -227,6 +227,14 @@ int best_set_whitening(best_ctx *h, const double *mu, const double *L);
 uint64_t best_get_step_counter(const best_ctx *h);
 int best_set_step_counter(best_ctx *h, uint64_t step);
 int best_set_step_size(best_ctx *h, double eps);
+/* Re-initialise every walker (Sec. 3.2 initialisation strategies, used by the burn-in loop
+ * that re-centres the ensemble on its best-fit point): BEST_INIT_UNIFORM in the prior box,
+ * BEST_INIT_REPLICATED at point, BEST_INIT_GAUSSIAN point + scale L xi with the CURRENT
+ * whitening factor L (xi from Philox stream 4 at the current step counter, which is not
+ * advanced).  point: host [d] inside the box (ignored for uniform).  log pi and its gradient
+ * are re-evaluated; the whitening and step size are kept.  Gaussian draws may fall outside
+ * the box (log pi = -inf there with the hard box). */
+int best_reinit(best_ctx *h, int32_t init, const double *point, double scale);
 /* Per-dimension step multipliers m (host [d], each finite and > 0; NULL removes them) for
  * the whitened-space MALA and MH transitions (Sec. 4.3: larger steps for chosen
  * dimensions): dimension i uses eps m_i in MALA's drift, noise and proposal density, and

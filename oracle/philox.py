@@ -95,17 +95,18 @@ def accept_uniform(seed, chains, step, sub=0):
     return ua
 
 
-def init_uniforms(seed, chains, d):
-    """Uniforms for walker initialisation: dim i from block i//2, member i%2 (step 0)."""
+def init_uniforms(seed, chains, d, step=0):
+    """Uniforms for walker initialisation: dim i from block i//2, member i%2 (step 0 at
+    the start, the current step counter when the walkers are re-initialised)."""
     chains = np.asarray(chains)
     nb = (d + 1) // 2
     out = np.empty((chains.shape[0], 2 * nb))
     for b in range(nb):
-        ua, ub = uniforms2(seed, chains, 0, STREAM_INIT, 0, b)
+        ua, ub = uniforms2(seed, chains, step, STREAM_INIT, 0, b)
         out[:, 2 * b] = ua
         out[:, 2 * b + 1] = ub
     return out[:, :d]
 
 
-def init_normals(seed, chains, d):
-    return normals(seed, chains, 0, STREAM_INIT, 1, d)
+def init_normals(seed, chains, d, step=0):
+    return normals(seed, chains, step, STREAM_INIT, 1, d)

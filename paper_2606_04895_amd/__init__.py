@@ -17,7 +17,8 @@ from ._abi import (BEST_AIES, BEST_BF16, BEST_FP16, BEST_FP32, BEST_FP64, BEST_H
 
 __all__ = ["BestError", "Ctx", "best_init", "best_logL_grad", "best_step", "best_adapt",
            "best_get_state", "best_set_state", "best_get_whitening", "best_set_whitening",
-           "best_set_step_size", "best_set_step_multipliers", "best_get_step_counter",
+           "best_set_step_size", "best_set_step_multipliers", "best_reinit",
+           "best_get_step_counter",
            "best_set_step_counter",
            "best_set_mlp", "best_ess", "best_rhat", "best_credible", "best_sliced_wasserstein",
            "best_mlp_nparams", "best_standardise",
@@ -277,6 +278,16 @@ def best_get_step_counter(ctx):
 
 def best_set_step_counter(ctx, step):
     ctx.check(_lib().best_set_step_counter(ctx.h, int(step)))
+
+
+def best_reinit(ctx, init="gaussian", point=None, scale=1.0):
+    """Re-initialise every walker (uniform / replicated / gaussian around point with the
+    current whitening factor)."""
+    modes = {"uniform": A.BEST_INIT_UNIFORM, "replicated": A.BEST_INIT_REPLICATED,
+             "gaussian": A.BEST_INIT_GAUSSIAN}
+    pa = _f64(point)
+    ctx.check(_lib().best_reinit(ctx.h, modes[init] if isinstance(init, str) else int(init),
+                                 _dptr(pa), float(scale)))
 
 
 def best_set_step_multipliers(ctx, m):

@@ -93,6 +93,7 @@ EXPORTS = {
     "best_set_step_counter": (C.c_int, [C.c_void_p, C.c_uint64]),
     "best_set_step_size": (C.c_int, [C.c_void_p, C.c_double]),
     "best_set_step_multipliers": (C.c_int, [C.c_void_p, _dp]),
+    "best_reinit": (C.c_int, [C.c_void_p, C.c_int32, _dp, C.c_double]),
     "best_set_mlp": (C.c_int, [C.c_void_p, _dp, C.c_double, C.c_double]),
     "best_ess": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, _dp]),
     "best_rhat": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, _dp]),

@@ -518,7 +518,7 @@ int best_init(best_ctx** out, const best_problem* p, const best_config* c) {
     return bail(fail(h, BEST_ENOMEM, "init point"));
   Rng rng{(uint32_t)(h->seed & 0xFFFFFFFFu), (uint32_t)(h->seed >> 32)};
   if (hipError_t e = launch_init_positions(h->tg, h->st, rng, c->init, pt_dev, c->init_scale,
-                                           h->L, h->stream))
+                                           h->L, 0, h->stream))
     return bail(fail_hip(h, "init positions", e));
   if ((rc = refresh_state(h))) return bail(rc);
   if ((rc = rewhiten(h))) return bail(rc);
@@ -837,6 +837,34 @@ int best_set_step_size(best_ctx* h, double eps) {
   da[0] = std::log(10.0 * eps);
   da[1] = da[2] = da[3] = 0;
   HIPCHK(h, hipMemcpy(h->da, da, sizeof(da), hipMemcpyHostToDevice));
+  return BEST_OK;
+}
+
+int best_reinit(best_ctx* h, int32_t init, const double* point, double scale) {
+  if (!h) return BEST_EINVAL;
+  if (init < BEST_INIT_UNIFORM || init > BEST_INIT_GAUSSIAN)
+    return fail(h, BEST_EINVAL, "unknown init mode");
+  if (init != BEST_INIT_UNIFORM && !point) return fail(h, BEST_EINVAL, "point is NULL");
+  if (init == BEST_INIT_GAUSSIAN && !(scale >= 0 && std::isfinite(scale)))
+    return fail(h, BEST_EINVAL, "scale must be finite and >= 0");
+  const int d = h->d;
+  for (int i = 0; point && i < d; ++i)
+    if (!(point[i] >= h->lower[i] && point[i] <= h->upper[i]))
+      return fail(h, BEST_EINVAL, "point outside the prior box");
+  double* pt_dev = nullptr;
+  std::vector<double> pt(point ? point : h->lower.data(), (point ? point : h->lower.data()) + d);
+  if (h->mem.upload(&pt_dev, pt.data(), d, h->stream) != hipSuccess)
+    return fail(h, BEST_ENOMEM, "point");
+  const Rng rng{(uint32_t)(h->seed & 0xFFFFFFFFu), (uint32_t)(h->seed >> 32)};
+  hipError_t e = launch_init_positions(h->tg, h->st, rng, init, pt_dev, scale, h->L, h->step,
+                                       h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  h->mem.release(pt_dev);
+  if (e != hipSuccess) return fail_hip(h, "reinit positions", e);
+  int rc;
+  if ((rc = refresh_state(h))) return rc;
+  if ((rc = rewhiten(h))) return rc;
+  HIPCHK(h, hipStreamSynchronize(h->stream));
   return BEST_OK;
 }
 

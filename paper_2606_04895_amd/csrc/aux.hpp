@@ -19,7 +19,7 @@ hipError_t launch_train_tile(int prec, int MT, const TrainArgs& a, int grid, siz
 // kernels_aux.hip
 hipError_t launch_init_positions(const Target& tg, const State& S, const Rng& rng, int mode,
                                  const double* pt, double scale, const double* L0,
-                                 hipStream_t s);
+                                 uint64_t step, hipStream_t s);
 hipError_t launch_rewhiten(const State& S, const Whiten& W, int d, hipStream_t s);
 hipError_t launch_da_update(const double* step_prob, int64_t N, double* da, hipStream_t s);
 hipError_t launch_stats(const State& S, int64_t* out_i, double* out_d, hipStream_t s);

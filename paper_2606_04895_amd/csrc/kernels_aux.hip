@@ -7,7 +7,7 @@ namespace best {
 
 // ---- walker initialisation (Sec. 3.2: uniform / replicated / Gaussian) ----------------
 __global__ void init_positions_kernel(Target tg, State S, Rng rng, int mode, const double* pt,
-                                      double scale, const double* L0) {
+                                      double scale, const double* L0, uint64_t step) {
   const int d = tg.d;
   const int64_t n = (int64_t)d * S.N;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
@@ -16,14 +16,14 @@ __global__ void init_positions_kernel(Target tg, State S, Rng rng, int mode, con
     const int64_t c = e % S.N;
     double v;
     if (mode == 0) {
-      const U4 b = rng.block(c, 0, kStreamInit, 0, (uint32_t)(i >> 1));
+      const U4 b = rng.block(c, step, kStreamInit, 0, (uint32_t)(i >> 1));
       const double u = (i & 1) ? u52(b.z, b.w) : u52(b.x, b.y);
       v = tg.lower[i] + (tg.upper[i] - tg.lower[i]) * u;
     } else if (mode == 1) {
       v = pt[i];
     } else {
       double s = 0;
-      for (int j = 0; j <= i; ++j) s += L0[i * d + j] * normal_dim(rng, c, 0, kStreamInit, 1, j);
+      for (int j = 0; j <= i; ++j) s += L0[i * d + j] * normal_dim(rng, c, step, kStreamInit, 1, j);
       v = pt[i] + scale * s;
     }
     S.x[i * S.Np + c] = v;
@@ -467,9 +467,9 @@ static int grid_for(int64_t n) {
 
 hipError_t launch_init_positions(const Target& tg, const State& S, const Rng& rng, int mode,
                                  const double* pt, double scale, const double* L0,
-                                 hipStream_t s) {
+                                 uint64_t step, hipStream_t s) {
   hipLaunchKernelGGL(init_positions_kernel, dim3(grid_for((int64_t)tg.d * S.N)),
-                     dim3(kAuxThreads), 0, s, tg, S, rng, mode, pt, scale, L0);
+                     dim3(kAuxThreads), 0, s, tg, S, rng, mode, pt, scale, L0, step);
   return hipGetLastError();
 }
 

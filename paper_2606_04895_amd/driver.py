@@ -17,8 +17,8 @@ import time
 
 import numpy as np
 
-from . import (best_adapt, best_ess, best_init, best_logL_grad, best_set_mlp,
-               best_set_step_size, best_standardise, best_step, Trainer)
+from . import (best_adapt, best_ess, best_get_state, best_init, best_logL_grad, best_reinit,
+               best_set_mlp, best_set_step_size, best_standardise, best_step, Trainer)
 
 TARGET_ACCEPT = {"mala": 0.57, "hmc": 0.8, "nuts": 0.8}
 EPS0 = {"mala": 0.5, "hmc": 0.3, "nuts": 0.5}
@@ -61,7 +61,15 @@ SCHEDULE = {"mala": "doubling", "mh": "doubling", "hmc": "thirds", "nuts": "doub
 
 
 def burn_in(ctx, sampler, warmup, d, n, n_leap=10, mh_scale=None, stretch_a=2.0,
-            schedule=None, max_depth=8):
+            schedule=None, max_depth=8, recenter=False, trajectory=None):
+    """Burn-in with covariance windows (and dual averaging for the gradient samplers).
+
+    recenter: after each covariance window, re-initialise the ensemble as Gaussian draws
+    around its best-fit walker (largest log pi) with the new whitening, the burn-in loop of
+    Sec. 4 in which the covariance and the best-fit point are updated together.
+    trajectory: a list that receives every window's record ([w][d][n] device floats; for
+    AIES and DE the whole burn-in run), the burn-in trajectories of the results object of
+    Sec. 3.1."""
     import torch
 
     schedule = schedule or SCHEDULE.get(sampler, "doubling")
@@ -71,13 +79,18 @@ def burn_in(ctx, sampler, warmup, d, n, n_leap=10, mh_scale=None, stretch_a=2.0,
     t0 = time.perf_counter()
     if sampler in ("aies", "de"):
         if warmup:
-            best_step(ctx, sampler, warmup, **kw)
+            rec = torch.empty((warmup, d, n), dtype=torch.float32, device="cuda") \
+                if trajectory is not None else None
+            best_step(ctx, sampler, warmup, record=rec, **kw)
+            if rec is not None:
+                trajectory.append(rec)
         return time.perf_counter() - t0
     gradient = sampler in TARGET_ACCEPT
     if gradient:
         best_set_step_size(ctx, EPS0[sampler])
     for w, update_cov in window_plan(warmup, schedule):
-        rec = torch.empty((w, d, n), dtype=torch.float32, device="cuda") if update_cov else None
+        rec = torch.empty((w, d, n), dtype=torch.float32, device="cuda") \
+            if (update_cov or trajectory is not None) else None
         if gradient:
             st = best_step(ctx, sampler, w, record=rec, adapt_eps=True,
                            target_accept=TARGET_ACCEPT[sampler], **kw)
@@ -87,9 +100,14 @@ def burn_in(ctx, sampler, warmup, d, n, n_leap=10, mh_scale=None, stretch_a=2.0,
             keep = rec[w // 2:] if w >= 4 else rec
             best_adapt(ctx, samples=keep.contiguous(), update_mean=True, finalize_da=gradient,
                        reset_da=gradient, target_accept=TARGET_ACCEPT.get(sampler, 0.0))
+            if recenter:
+                x, lp, _ = best_get_state(ctx)
+                best_reinit(ctx, "gaussian", x[:, int(np.argmax(lp))], 1.0)
         elif gradient:
             # step size only: the averaged iterate, dual averaging restarted from it
             best_set_step_size(ctx, st["eps_bar"])
+        if trajectory is not None and rec is not None:
+            trajectory.append(rec)
         del rec
     torch.cuda.synchronize()
     return time.perf_counter() - t0

@@ -160,3 +160,49 @@ def test_step_multipliers_lockstep(sampler, kw, arg):
         B.best_set_step_multipliers(ctx, np.array([1.0, 0.0, 1.0, 1.0, 1.0]))
     assert e.value.code == 1
     ctx.close()
+
+
+def test_reinit_matches_the_oracle_generators():
+    """best_reinit: uniform draws in the box, the replicated point, and point + scale L xi
+    with the current whitening factor, xi from the init stream at the step counter."""
+    prob = small_problem(d=5, width=128, n_hidden=3, twist=True)
+    seed = 0xBE5B
+    ctx = B.best_init(prob, n_chains=37, precision="fp32", seed=seed)
+    L = np.linalg.cholesky(prob["closed_cov"])
+    B.best_set_whitening(ctx, prob["gauss_mean"], L)
+    B.best_step(ctx, "mh", 3, mh_scale=0.3)
+    t = B.best_get_step_counter(ctx)
+    ids = np.arange(37, dtype=np.uint64)
+    B.best_reinit(ctx, "gaussian", prob["gauss_mean"], 0.7)
+    x, lp, g = B.best_get_state(ctx)
+    _, Lc = B.best_get_whitening(ctx)
+    ref = prob["gauss_mean"][None, :] + 0.7 * OP.init_normals(seed, ids, 5, step=t) @ Lc.T
+    np.testing.assert_allclose(x.T, ref, rtol=1e-12, atol=1e-12)
+    lo, go = OT.log_target(prob, x.T)
+    assert np.max(np.abs(lp - lo) / (1 + np.abs(lo))) < 2e-5
+    B.best_reinit(ctx, "uniform")
+    ref = prob["lower"] + (prob["upper"] - prob["lower"]) * OP.init_uniforms(seed, ids, 5, step=t)
+    np.testing.assert_allclose(B.best_get_state(ctx)[0].T, ref, rtol=1e-12, atol=1e-12)
+    B.best_reinit(ctx, "replicated", prob["gauss_mean"])
+    assert np.array_equal(B.best_get_state(ctx)[0].T, np.tile(prob["gauss_mean"], (37, 1)))
+    with pytest.raises(B.BestError):
+        B.best_reinit(ctx, "replicated", prob["upper"] + 1.0)
+    ctx.close()
+
+
+def test_recentring_burn_in_and_trajectory():
+    """Burn-in that re-centres the ensemble on its best-fit walker after every covariance
+    window, keeping the trajectory; the Gaussian posterior mean is then recovered."""
+    from paper_2606_04895_amd import driver
+    from workloads import make_problem
+    prob = make_problem("c2", with_mlp=False)
+    n, d = 2048, 6
+    ctx = B.best_init(prob, n_chains=n, precision="fp32", seed=5, init="uniform")
+    traj = []
+    driver.burn_in(ctx, "mala", 300, d, n, recenter=True, trajectory=traj)
+    assert sum(int(r.shape[0]) for r in traj) == 300
+    st, rec, wall, ess = driver.sample(ctx, "mala", 300, d, n)
+    m = rec.double().mean(dim=(0, 2)).cpu().numpy()
+    sd = np.sqrt(np.diag(prob["closed_cov"]))
+    assert np.all(np.abs(m - prob["closed_mean"]) / (sd / np.sqrt(ess)) < 5)
+    ctx.close()
