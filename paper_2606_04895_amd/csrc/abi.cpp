@@ -172,6 +172,9 @@ struct best_ctx {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   double* nu_buf = nullptr;  // NUTS trajectory buffers (allocated by the first NUTS call)
   double* mult = nullptr;    // per-dimension step multipliers [d] (MALA, MH)
+  bool mt_fixed = false;     // tile width set by the caller (chains_per_block)
+  char* ev_hsave = nullptr;  // activation scratch of wider evaluation tiles
+  size_t ev_hsave_bytes = 0;
   bool mult_on = false;
   NutsState nu{};
   std::vector<double> lower, upper;
@@ -219,10 +222,44 @@ static int run_eval(best_ctx* h, const double* X, int64_t pitch, int64_t n, doub
   a.ex_lp = LP;
   a.ex_g = G;
   a.ex_grad = G != nullptr;
-  const int64_t M = 16 * h->MT;
+  int mt = h->MT, grid_cap = h->grid_cap;
+  size_t lds = h->lds.total;
+  if (!h->mt_fixed) {
+    // a batch larger than the chain ensemble gets the widest tile that still gives every CU
+    // a tile of the batch (the rule the context applied to its chains); never narrower
+    int best = 0;
+    for (int m = 1; m <= mt_max(h->prec); m *= 2) {
+      if (layout_for(h->prec, m, h->H, h->d, h->nh, 0).total > kLdsMax) break;
+      if (best && (n + 16 * m - 1) / (16 * m) < h->n_cu) break;
+      best = m;
+    }
+    if (best > h->MT) {
+      mt = best;
+      const int lh = layout_for(h->prec, mt, h->H, h->d, h->nh, 1).total <= kLdsMax ? 1 : 0;
+      const LdsLayout lay = layout_for(h->prec, mt, h->H, h->d, h->nh, lh);
+      grid_cap = h->n_cu * std::max(1, std::min(2, kLdsMax / lay.total));
+      a.mp.lds_h = lh;
+      a.lds = lay;
+      lds = lay.total;
+      a.hsave_stride = (int64_t)h->nh * h->H * 16 * mt;
+      if (!lh) {
+        const size_t need = (size_t)grid_cap * a.hsave_stride * vasize(h->prec);
+        if (need > h->ev_hsave_bytes) {
+          h->mem.release(h->ev_hsave);
+          h->ev_hsave = nullptr;
+          h->ev_hsave_bytes = 0;
+          if (h->mem.alloc(&h->ev_hsave, need) != hipSuccess)
+            return fail(h, BEST_ENOMEM, "evaluation activation scratch");
+          h->ev_hsave_bytes = need;
+        }
+        a.hsave = h->ev_hsave;
+      }
+    }
+  }
+  const int64_t M = 16 * mt;
   a.n_tiles = (n + M - 1) / M;
-  const int grid = (int)std::min<int64_t>(a.n_tiles, h->grid_cap);
-  HIPCHK(h, launch_eval(h->prec, h->MT, a, grid, h->lds.total, h->stream));
+  const int grid = (int)std::min<int64_t>(a.n_tiles, grid_cap);
+  HIPCHK(h, launch_eval(h->prec, mt, a, grid, lds, h->stream));
   return BEST_OK;
 }
 
@@ -348,6 +385,7 @@ static int choose_mt(best_ctx* h, const best_config* c) {
     if (!mt) return fail(h, BEST_EINVAL, "MLP width too large for the LDS budget");
   }
   h->MT = mt;
+  h->mt_fixed = c->chains_per_block != 0;
   h->lds_h = fits(mt, 1) ? 1 : 0;
   // the sampler's per-step FP64 scratch goes to LDS too when there is room
   h->st_lds = layout_for(h->prec, mt, h->H, h->d, h->nh, h->lds_h, 1).total <= kLdsMax ? 1 : 0;

@@ -3,6 +3,7 @@
 * throughput sweep: standalone best_logL_grad evaluations per second against the number of
   points N for the C2, C3 and C5 networks in BF16 and FP32 (the batched-evaluation curve of
   the paper's Fig. 1, re-measured), and HMC evaluations per second inside the sampler;
+* NUTS on the C2 workload: leaves per transition and useful evaluations per second;
 * the BF16 / FP32 pair on the C3 network at 4096 chains;
 * BF16 accuracy: the error of BF16 log pi against the FP64 GEMM path on posterior samples,
   and the posterior moments of BF16 chains against FP32 chains on the C2 workload.
@@ -96,6 +97,21 @@ def main():
                 rate = hmc_rate(B, prob, prec, n)
                 emit(dict(kind="hmc_rate", net=f"{d}->{H}x{nh}->1", config=name, prec=prec, n=n,
                           evals_per_s=rate, tflops=rate * _flops(d, H, nh) / 1e12))
+
+    # ---- NUTS on the C2 workload at 4096 chains: leaves per transition and the useful
+    #      evaluation rate of the lockstep tiles against HMC's on the same ensemble ----
+    prob = make_problem("c2")
+    ctx = B.best_init(prob, n_chains=4096, precision="bf16", seed=9, init="uniform")
+    driver.burn_in(ctx, "nuts", 300, prob["d"], 4096)
+    st = B.best_step(ctx, "nuts", 20 if args.quick else 100, max_depth=8)
+    steps = 20 if args.quick else 100
+    hm = B.best_step(ctx, "hmc", 20, eps=st["eps"], n_leapfrog=10)
+    emit(dict(kind="nuts_rate", config="c2", prec="bf16", n=4096, steps=steps,
+              leaves_per_transition=st["evals"] / (steps * 4096),
+              evals_per_s=st["evals"] / (st["ms"] * 1e-3), eps=st["eps"],
+              accept_stat=st["sum_accept_prob"] / (steps * 4096),
+              hmc_evals_per_s=hm["evals"] / (hm["ms"] * 1e-3)))
+    ctx.close()
 
     # ---- host-pointer mode (PCIe copies inside the call) on C2 at 4096 points ----
     prob = make_problem("c2")

@@ -206,3 +206,31 @@ def test_recentring_burn_in_and_trajectory():
     sd = np.sqrt(np.diag(prob["closed_cov"]))
     assert np.all(np.abs(m - prob["closed_mean"]) / (sd / np.sqrt(ess)) < 5)
     ctx.close()
+
+
+@pytest.mark.parametrize("cfg,prec,n,tl,tg", [("c2", "bf16", 40000, 2e-2, None),
+                                             ("c2", "fp32", 40000, 2e-5, 2e-4),
+                                             ("c5", "bf16", 20000, 2e-2, None)])
+def test_large_batch_eval_on_wider_tiles(cfg, prec, n, tl, tg):
+    """A batch far larger than the context's chains is evaluated on the widest tile that
+    still fills the CUs (C5 BF16: 32-chain tiles with the activations in global scratch);
+    sampled points against the oracle; log pi bitwise equal to the context's own tile width
+    (BF16 gradients may differ in rounding where the narrow tile keeps the activations in
+    LDS in BF16 and the wide one in FP32 global scratch)."""
+    from workloads import make_problem
+    prob = make_problem(cfg)
+    x = _pts(prob, n, 5)
+    ctx = B.best_init(prob, n_chains=16, precision=prec, seed=1)
+    lp, g = B.best_logL_grad(ctx, x.T.copy())
+    ctx.close()
+    narrow = B.best_init(prob, n_chains=16, precision=prec, seed=1, chains_per_block=16)
+    lp16, g16 = B.best_logL_grad(narrow, x.T.copy())
+    narrow.close()
+    assert np.array_equal(lp, lp16)
+    if prec == "fp32":  # same activation storage at both widths: identical gradients too
+        assert np.array_equal(g, g16)
+    idx = np.random.default_rng(7).choice(n, 150, replace=False)
+    lo, go = OT.log_target(prob, x[idx])
+    assert np.max(np.abs(lp[idx] - lo) / (1 + np.abs(lo))) < tl
+    if tg is not None:
+        assert np.max(np.abs(g[:, idx].T - go) / (1 + np.abs(go))) < tg
