@@ -1,4 +1,5 @@
-"""Multi-chain effective sample size (the build's throughput metric; not in the paper).
+"""Multi-chain effective sample size (the throughput metric reported with the samplers; not in
+the paper).
 
 For one parameter with M chains of length T (x_{m,t}):
     chain means xbar_m, within-chain variance W = mean_m s_m^2 (1/(T-1)),

@@ -1,8 +1,8 @@
 """Emulator training, importance weights and Kish ESS, in float64.
 
 Not in the paper itself (its emulators come from the CLiENT framework it cites); this is the
-learned part of the build: an MLP is fitted to (theta, logL) pairs that the plain spectrum
-model produces, then used as the sampling target, and the plain likelihood judges it.
+learned part of the method here: an MLP is fitted to (theta, logL) pairs that the plain spectrum
+model produces, then used as the sampling target, and the plain likelihood assesses it.
 
   standardise     y_hat = (y - y_mu) / y_sigma (population std);  emulator logL = y_mu + y_sigma MLP
   loss            mean over the minibatch of (MLP(theta_hat_c) - y_hat_c)^2

@@ -1,7 +1,7 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the same seeded
 inputs and the same Philox streams.
 
-Tolerances (stated here, derived in the design doc):
+Tolerances (from the rounding of each GEMM type; the FP64 accept arithmetic is common):
   FP64 GEMMs  logL abs 1e-9 * (1 + |logL|), grad rel 1e-8
   FP32 GEMMs  logL abs 2e-5 * (1 + |logL|), grad abs 2e-4 * (1 + |g|)
   FP16 / BF16 the emulator term (coef * MLP) within 2e-2 (bf16) / 4e-3 (fp16) absolute
