@@ -1,6 +1,7 @@
 """Sampler comparison on the 27-parameter workload (6 cosmological-like + 21 linear nuisance
-parameters, Gaussian part plus a 27 -> 1024 x 5 -> 1 tanh emulator in BF16 GEMMs): AIES
-(stretch move, a = 2, two half-ensembles), NUTS (maximum depth 8) and MALA, each after its
+parameters, Gaussian part plus a 27 -> 1024 x 5 -> 1 tanh emulator in BF16 GEMMs; --config c3
+gives the 12-parameter twisted target of the second experiment): AIES (stretch move, a = 2,
+two half-ensembles), NUTS (maximum depth 8), MALA and HMC (10 leapfrog steps), each after its
 own burn-in with covariance and (for the gradient samplers) step-size adaptation, compared on
 min-ESS/s (the smallest multi-chain ESS over the parameters divided by the production wall
 time), on emulator evaluations per second, and on the convergence metrics of Sec. 4.1: R - 1
@@ -40,6 +41,11 @@ def main():
     ap.add_argument("--quick", action="store_true")
     ap.add_argument("--sw-steps", type=int, default=8,
                     help="last steps of each run whose draws enter the sliced Wasserstein")
+    ap.add_argument("--recenter", action="store_true",
+                    help="re-centre the ensemble on its best-fit walker after each covariance "
+                         "window of the burn-in (gradient samplers, MH and the reference)")
+    ap.add_argument("--scale", type=float, default=1.0,
+                    help="multiply every warm-up and production length")
     args = ap.parse_args()
     import torch
     import paper_2606_04895_amd as B
@@ -51,10 +57,12 @@ def main():
     plan = {  # (warm-up steps, production steps)
         "aies": (2000, 2000),
         "mala": (1000, 2000),
+        "hmc": (1000, 1000),
         "nuts": (400, 300),
     }
     if args.quick:
         plan = {k: (max(50, w // 10), max(50, s // 10)) for k, (w, s) in plan.items()}
+    plan = {k: (int(w * args.scale), int(s * args.scale)) for k, (w, s) in plan.items()}
     results = []
 
     def emit(obj):
@@ -63,13 +71,15 @@ def main():
 
     def run(sampler, seed, warm, steps):
         ctx = B.best_init(prob, n_chains=n, precision=args.precision, seed=seed, init="uniform")
-        t_burn = driver.burn_in(ctx, sampler, warm, d, n, max_depth=args.max_depth)
+        t_burn = driver.burn_in(ctx, sampler, warm, d, n, max_depth=args.max_depth,
+                                recenter=args.recenter)
         st, rec, wall, ess = driver.sample(ctx, sampler, steps, d, n, max_depth=args.max_depth)
         return ctx, st, rec, wall, ess, t_burn
 
     # reference posterior: two independent long MALA runs (the second sets the noise floor of
     # the credible metric and the sliced Wasserstein distance, as in Sec. 4.1)
     ref_warm, ref_steps = (200, 400) if args.quick else (2000, 4000)
+    ref_warm, ref_steps = int(ref_warm * args.scale), int(ref_steps * args.scale)
     ref = {}
 
     def metrics(ctx, prod, tail):

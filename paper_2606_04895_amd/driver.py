@@ -21,6 +21,10 @@ from . import (best_adapt, best_ess, best_get_state, best_init, best_logL_grad, 
                best_set_mlp, best_set_step_size, best_standardise, best_step, Trainer)
 
 TARGET_ACCEPT = {"mala": 0.57, "hmc": 0.8, "nuts": 0.8}
+# Dual averaging lowers the step size without bound while nothing is accepted (chains far in
+# the tails of a sharply curved target); between windows it is kept at or above this floor
+# so that a window never starts from a step size that has underflowed to zero.
+EPS_FLOOR = 1e-12
 EPS0 = {"mala": 0.5, "hmc": 0.3, "nuts": 0.5}
 
 
@@ -98,14 +102,17 @@ def burn_in(ctx, sampler, warmup, d, n, n_leap=10, mh_scale=None, stretch_a=2.0,
             st = best_step(ctx, sampler, w, record=rec, **kw)
         if update_cov:
             keep = rec[w // 2:] if w >= 4 else rec
-            best_adapt(ctx, samples=keep.contiguous(), update_mean=True, finalize_da=gradient,
-                       reset_da=gradient, target_accept=TARGET_ACCEPT.get(sampler, 0.0))
+            info = best_adapt(ctx, samples=keep.contiguous(), update_mean=True,
+                              finalize_da=gradient, reset_da=gradient,
+                              target_accept=TARGET_ACCEPT.get(sampler, 0.0))
+            if gradient and not info["eps"] >= EPS_FLOOR:
+                best_set_step_size(ctx, EPS_FLOOR)
             if recenter:
                 x, lp, _ = best_get_state(ctx)
                 best_reinit(ctx, "gaussian", x[:, int(np.argmax(lp))], 1.0)
         elif gradient:
             # step size only: the averaged iterate, dual averaging restarted from it
-            best_set_step_size(ctx, st["eps_bar"])
+            best_set_step_size(ctx, max(st["eps_bar"], EPS_FLOOR))
         if trajectory is not None and rec is not None:
             trajectory.append(rec)
         del rec
