@@ -200,8 +200,11 @@ def best_logL_grad(ctx, x, want_grad=True, out=None):
 def best_step(ctx, sampler, n_steps, eps=0.0, mh_scale=0.0, stretch_a=2.0, n_leapfrog=10,
               thin=1, record=None, adapt_eps=False, target_accept=0.57, max_depth=8,
               de_sigma=0.1):
-    """Advance every chain n_steps transitions.  record: CUDA float32 tensor
-    [capacity][d][n_chains] or None.  Returns the call's statistics as a dict."""
+    """Advance every chain n_steps transitions of sampler "mh", "mala", "hmc", "nuts", "aies"
+    or "de".  eps <= 0 uses the context's step size (dual averaging with adapt_eps);
+    n_leapfrog: HMC; max_depth: NUTS; stretch_a: AIES; de_sigma: sd of the DE gamma noise.
+    record: CUDA float32 tensor [capacity][d][n_chains] or None.  Returns the call's
+    statistics as a dict (for NUTS, evals counts the leaves of the trajectories)."""
     lib = _lib()
     p = A.StepParams()
     p.eps, p.mh_scale, p.stretch_a = float(eps), float(mh_scale), float(stretch_a)
