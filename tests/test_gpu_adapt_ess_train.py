@@ -219,3 +219,25 @@ def test_autograd_wrapper_returns_the_hand_written_gradient():
     _, go = OT.log_target(prob, x)
     ref = go * np.arange(1, 21)[:, None]
     np.testing.assert_allclose(xt.grad.cpu().numpy().T, ref, rtol=2e-4, atol=2e-4)
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_half_precision_chains_match_fp32_posterior(prec):
+    """The 16-bit GEMM step kernels end to end on the C2 workload (with the emulator term):
+    HMC chains in FP16 / BF16 and in FP32 from the same adapted start reach posterior means
+    that agree within 5 Monte-Carlo errors and marginal sds within 5%."""
+    from paper_2606_04895_amd import driver
+    prob = make_problem("c2")
+    n, d = 4096, 6
+    out = {}
+    for p in ("fp32", prec):
+        ctx = _ctx_at_mean(prob, n, prec=p, seed=8)
+        driver.burn_in(ctx, "hmc", 200, d, n)
+        st, rec, wall, ess = driver.sample(ctx, "hmc", 300, d, n)
+        r = rec.double()
+        out[p] = (r.mean(dim=(0, 2)).cpu().numpy(), r.std(dim=(0, 2)).cpu().numpy(), ess.min())
+        ctx.close()
+    (m32, s32, e32), (m16, s16, e16) = out["fp32"], out[prec]
+    tol = 5 * s32 * np.sqrt(1.0 / e32 + 1.0 / e16)
+    assert np.all(np.abs(m16 - m32) < tol), (np.abs(m16 - m32) / s32, tol / s32)
+    assert np.all(np.abs(s16 / s32 - 1) < 0.05)
