@@ -197,12 +197,20 @@ def test_lockstep_c1_fp64_mh():
 def test_bitwise_determinism_across_runs_and_tile_widths():
     prob = small_problem(d=5, width=128, n_hidden=3)
     outs = []
-    for cpb in (16, 32, 16):
+    for cpb in (16, 32, 16, 64):
         ctx = B.best_init(prob, n_chains=200, precision="fp32", seed=9, chains_per_block=cpb)
         B.best_step(ctx, "mala", 7, eps=0.3)
         outs.append(B.best_get_state(ctx)[0])
     assert np.array_equal(outs[0], outs[2])
     assert np.array_equal(outs[0], outs[1])
+    assert np.array_equal(outs[0], outs[3])
+    # the 16-bit HMC kernel at 16- and 64-chain tiles (activations in LDS at both widths)
+    hm = []
+    for cpb in (16, 64):
+        ctx = B.best_init(prob, n_chains=200, precision="bf16", seed=9, chains_per_block=cpb)
+        B.best_step(ctx, "hmc", 4, eps=0.1, n_leapfrog=5)
+        hm.append(B.best_get_state(ctx)[0])
+    assert np.array_equal(hm[0], hm[1])
 
 
 def test_resume_from_checkpoint_is_bitwise():
