@@ -19,9 +19,9 @@ from workloads import make_problem, small_problem
 pytestmark = pytest.mark.gpu
 
 
-def _lockstep_nuts(prob, n, eps, max_depth, steps, seed, init_scale=0.05):
+def _lockstep_nuts(prob, n, eps, max_depth, steps, seed, init_scale=0.05, cpb=0):
     ctx = B.best_init(prob, n_chains=n, precision="fp32", seed=seed, init="gaussian",
-                      init_point=prob["gauss_mean"], init_scale=init_scale)
+                      init_point=prob["gauss_mean"], init_scale=init_scale, chains_per_block=cpb)
     B.best_set_whitening(ctx, prob["gauss_mean"], np.linalg.cholesky(prob["closed_cov"]))
     mism, total, depths = 0, 0, []
     for _ in range(steps):
@@ -64,6 +64,13 @@ def test_lockstep_depth_limit_reached():
     prob = small_problem(d=5, width=128, n_hidden=3, twist=True)
     depths = _lockstep_nuts(prob, 20, 0.001, 4, steps=2, seed=0xBE62)
     assert np.all(depths == 4)
+
+
+@pytest.mark.parametrize("cpb", [64, 16])
+def test_lockstep_27_parameters_wide_tiles(cpb):
+    """d = 27 (lane groups of 32 lanes per chain, 5 of them idle) in 64- and 16-chain tiles."""
+    prob = small_problem(d=27, width=128, n_hidden=2, seed=11)
+    _lockstep_nuts(prob, 70, 0.3, 6, steps=2, seed=0xBE71, cpb=cpb)
 
 
 def test_lockstep_c2_network():
