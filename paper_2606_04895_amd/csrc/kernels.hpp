@@ -490,18 +490,32 @@ __device__ __forceinline__ double accept_prob(double la) {
   return isnan(la) ? 0.0 : exp(fmin(0.0, la));
 }
 
+// Per-chain statistics of a launch, kept in the registers of the thread that owns the chain
+// (thread c of the tile for chain c0 + c in every step) and added to the state at the end.
+struct Tally {
+  uint32_t acc, nonfinite, oob;
+  double sum_prob, last_prob;
+};
+
+__device__ __forceinline__ void flush_tally(const State& S, int64_t ch, const Tally& ty) {
+  S.n_acc[ch] += ty.acc;
+  S.n_nonfinite[ch] += ty.nonfinite;
+  S.n_oob[ch] += ty.oob;
+  S.sum_prob[ch] += ty.sum_prob;
+  S.step_prob[ch] = ty.last_prob;
+}
+
 // Accept bookkeeping for chain ch of the tile (called by one thread per chain).
-__device__ __forceinline__ bool decide(const KArgs& a, int64_t ch, uint64_t t, uint32_t sub,
-                                       double la, double lpp, int inbox) {
-  const State& S = a.st;
+__device__ __forceinline__ bool decide(const KArgs& a, Tally& ty, int64_t ch, uint64_t t,
+                                       uint32_t sub, double la, double lpp, int inbox) {
   const double u = accept_uniform(a.rng, ch, t, sub);
   const bool acc = log(u) < la;
   const double pr = accept_prob(la);
-  S.n_acc[ch] += acc ? 1u : 0u;
-  S.sum_prob[ch] += pr;
-  S.step_prob[ch] = pr;
-  S.n_nonfinite[ch] += isnan(lpp) ? 1u : 0u;
-  S.n_oob[ch] += inbox ? 0u : 1u;
+  ty.acc += acc ? 1u : 0u;
+  ty.sum_prob += pr;
+  ty.last_prob = pr;
+  ty.nonfinite += isnan(lpp) ? 1u : 0u;
+  ty.oob += inbox ? 0u : 1u;
   return acc;
 }
 
@@ -536,7 +550,7 @@ __device__ __forceinline__ void commit_tile(const State& S, const Scratch& T, co
 // ---------------------------------------------------------------------------------------
 template <class P, int MT>
 __device__ __forceinline__ void mh_tile(const KArgs& a, char* smem, typename P::acc* hsave,
-                                        int64_t c0, int mv, uint64_t t) {
+                                        Tally& ty, int64_t c0, int mv, uint64_t t) {
   constexpr int M = 16 * MT;
   const State& S = a.st;
   const int d = a.tg.d, tid = local_tid();
@@ -558,7 +572,7 @@ __device__ __forceinline__ void mh_tile(const KArgs& a, char* smem, typename P::
     const int64_t ch = c0 + tid;
     const double lpp = T.lpp[tid];
     const double la = lpp - S.lp[ch];
-    const bool acc = decide(a, ch, t, 0, la, lpp, inbox[tid]);
+    const bool acc = decide(a, ty, ch, t, 0, la, lpp, inbox[tid]);
     flag[tid] = acc;
     if (acc) S.lp[ch] = lpp;
   }
@@ -569,7 +583,7 @@ __device__ __forceinline__ void mh_tile(const KArgs& a, char* smem, typename P::
 
 template <class P, int MT>
 __device__ __forceinline__ void mala_tile(const KArgs& a, char* smem, typename P::acc* hsave,
-                                          int64_t c0, int mv, uint64_t t, double eps) {
+                                          Tally& ty, int64_t c0, int mv, uint64_t t, double eps) {
   constexpr int M = 16 * MT;
   const State& S = a.st;
   const int d = a.tg.d, tid = local_tid();
@@ -623,7 +637,7 @@ __device__ __forceinline__ void mala_tile(const KArgs& a, char* smem, typename P
     }
     const double lpp = T.lpp[c];
     const double la = lpp - S.lp[ch] + (-rev) - (-fwd);
-    const bool acc = decide(a, ch, t, 0, la, lpp, inbox[c]);
+    const bool acc = decide(a, ty, ch, t, 0, la, lpp, inbox[c]);
     flag[c] = acc;
     if (acc) S.lp[ch] = lpp;
   }
@@ -634,7 +648,7 @@ __device__ __forceinline__ void mala_tile(const KArgs& a, char* smem, typename P
 
 template <class P, int MT>
 __device__ __forceinline__ void hmc_tile(const KArgs& a, char* smem, typename P::acc* hsave,
-                                         int64_t c0, int mv, uint64_t t, double eps) {
+                                         Tally& ty, int64_t c0, int mv, uint64_t t, double eps) {
   constexpr int M = 16 * MT;
   const State& S = a.st;
   const int d = a.tg.d, tid = local_tid();
@@ -689,7 +703,7 @@ __device__ __forceinline__ void hmc_tile(const KArgs& a, char* smem, typename P:
     const double lp1 = (inbox[tid] || a.tg.box_penalty) ? T.lpp[tid] : -INFINITY;
     const double h1 = -lp1 + 0.5 * k;
     const double la = h0[tid] - h1;
-    const bool acc = decide(a, ch, t, 0, la, lp1, inbox[tid]);
+    const bool acc = decide(a, ty, ch, t, 0, la, lp1, inbox[tid]);
     flag[tid] = acc;
     if (acc) S.lp[ch] = lp1;
   }
@@ -701,7 +715,7 @@ __device__ __forceinline__ void hmc_tile(const KArgs& a, char* smem, typename P:
 // AIES: walkers of the active half [chain0, chain0 + half) against the other half.
 template <class P, int MT>
 __device__ __forceinline__ void aies_tile(const KArgs& a, char* smem, typename P::acc* hsave,
-                                          int64_t c0, int mv, uint64_t t) {
+                                          Tally& ty, int64_t c0, int mv, uint64_t t) {
   constexpr int M = 16 * MT;
   const State& S = a.st;
   const int d = a.tg.d, tid = local_tid();
@@ -734,7 +748,7 @@ __device__ __forceinline__ void aies_tile(const KArgs& a, char* smem, typename P
     const int64_t k = c0 + tid;
     const double lpp = T.lpp[tid];
     const double la = (double)(d - 1) * log(zz[tid]) + lpp - S.lp[k];
-    const bool acc = decide(a, k, t, (uint32_t)h, la, lpp, inbox[tid]);
+    const bool acc = decide(a, ty, k, t, (uint32_t)h, la, lpp, inbox[tid]);
     flag[tid] = acc;
     if (acc) S.lp[k] = lpp;
   }
@@ -991,7 +1005,7 @@ __device__ __forceinline__ void nuts_tile(const KArgs& a, char* smem, typename P
 // half: block 0 holds the two partner uniforms, block 1 the normal for eta.
 template <class P, int MT>
 __device__ __forceinline__ void de_tile(const KArgs& a, char* smem, typename P::acc* hsave,
-                                        int64_t c0, int mv, uint64_t t) {
+                                        Tally& ty, int64_t c0, int mv, uint64_t t) {
   constexpr int M = 16 * MT;
   const State& S = a.st;
   const int d = a.tg.d, tid = local_tid();
@@ -1021,7 +1035,7 @@ __device__ __forceinline__ void de_tile(const KArgs& a, char* smem, typename P::
   if (tid < mv) {
     const int64_t k = c0 + tid;
     const double lpp = T.lpp[tid];
-    const bool acc = decide(a, k, t, (uint32_t)h, lpp - S.lp[k], lpp, inbox[tid]);
+    const bool acc = decide(a, ty, k, t, (uint32_t)h, lpp - S.lp[k], lpp, inbox[tid]);
     flag[tid] = acc;
     if (acc) S.lp[k] = lpp;
   }
@@ -1082,15 +1096,19 @@ __global__ __launch_bounds__(kThreads, 1) void step_kernel(KArgs a) {
     constexpr bool kHalves = SAMPLER == 3 || SAMPLER == 5;  // ensemble moves, one half per launch
     const int64_t lim = kHalves ? a.chain0 + a.st.N / 2 : a.st.N;
     const int mv = (int)((lim - c0) < M ? (lim - c0) : M);
+    Tally ty{};
     for (int s = 0; s < a.n_steps; ++s) {
       const uint64_t t = (uint64_t)(a.step0 + s);
-      if constexpr (SAMPLER == 0) mh_tile<P, MT>(a, smem, hsave, c0, mv, t);
-      if constexpr (SAMPLER == 1) mala_tile<P, MT>(a, smem, hsave, c0, mv, t, eps);
-      if constexpr (SAMPLER == 2) hmc_tile<P, MT>(a, smem, hsave, c0, mv, t, eps);
-      if constexpr (SAMPLER == 3) aies_tile<P, MT>(a, smem, hsave, c0, mv, t);
+      if constexpr (SAMPLER == 0) mh_tile<P, MT>(a, smem, hsave, ty, c0, mv, t);
+      if constexpr (SAMPLER == 1) mala_tile<P, MT>(a, smem, hsave, ty, c0, mv, t, eps);
+      if constexpr (SAMPLER == 2) hmc_tile<P, MT>(a, smem, hsave, ty, c0, mv, t, eps);
+      if constexpr (SAMPLER == 3) aies_tile<P, MT>(a, smem, hsave, ty, c0, mv, t);
       if constexpr (SAMPLER == 4) nuts_tile<P, MT>(a, smem, hsave, c0, mv, t, eps);
-      if constexpr (SAMPLER == 5) de_tile<P, MT>(a, smem, hsave, c0, mv, t);
+      if constexpr (SAMPLER == 5) de_tile<P, MT>(a, smem, hsave, ty, c0, mv, t);
       if constexpr (!kHalves) record_tile(a, s, a.tg.d, M, mv, c0);
+    }
+    if constexpr (SAMPLER != 4) {
+      if (a.n_steps > 0 && local_tid() < mv) flush_tally(a.st, c0 + local_tid(), ty);
     }
   }
 }
