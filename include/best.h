@@ -245,10 +245,20 @@ int best_set_mlp(best_ctx *h, const double *params, double mlp_coef, double offs
 
 /* Multi-chain effective sample size of a record ([T][d][n_chains] device floats) per
  * parameter: rho_t = 1 - (W - mean_m gamma_{m,t}) / var+, Geyer initial monotone
- * sequence, tau = max(-1 + 2 sum P_k, 1 / log10(M T)), ESS = M T / tau.  Autocovariances
- * are summed directly on the device in FP64.
- * ess_out: host [d]. */
-int best_ess(best_ctx *h, const float *record, int64_t T, double *ess_out);
+ * sequence, tau = max(-1 + 2 sum P_k, 1 / log10(M T)), ESS = M T / tau (Geyer 1992;
+ * Vehtari et al. 2021; the throughput metric reported with the samplers, not the paper's).
+ * Autocovariances are summed directly on the device in FP64.  T >= 4.
+ * ess_out: host [d].  flags_out: host [d] or NULL, per parameter one of
+ *   BEST_ESS_OK          the pair sums turned non-positive inside the window;
+ *   BEST_ESS_UNTRUNCATED every pair sum the window holds is positive: the window is
+ *                        shorter than the autocorrelation, tau is a lower bound and the
+ *                        ESS an upper bound;
+ *   BEST_ESS_FROZEN      the within-chain variance W is 0 (every chain constant over the
+ *                        window, e.g. nothing accepted): no estimate exists, ESS = 0. */
+#define BEST_ESS_OK 0
+#define BEST_ESS_UNTRUNCATED 1
+#define BEST_ESS_FROZEN 2
+int best_ess(best_ctx *h, const float *record, int64_t T, double *ess_out, int32_t *flags_out);
 
 /* ---- convergence metrics (Sec. 4.1) ----
  * Samples are device records [T][d][n_chains] (floats, chain fastest), as best_step writes

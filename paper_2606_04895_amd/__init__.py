@@ -304,12 +304,19 @@ def best_set_mlp(ctx, params, mlp_coef, offset=0.0):
     ctx.check(_lib().best_set_mlp(ctx.h, _dptr(p), float(mlp_coef), float(offset)))
 
 
-def best_ess(ctx, record, n=None):
-    """record: CUDA float32 tensor [T][d][n_chains]; returns per-parameter ESS (numpy)."""
+ESS_FLAGS = {A.BEST_ESS_OK: "ok", A.BEST_ESS_UNTRUNCATED: "untruncated",
+             A.BEST_ESS_FROZEN: "frozen"}
+
+
+def best_ess(ctx, record, n=None, flags=False):
+    """record: CUDA float32 tensor [T][d][n_chains]; returns per-parameter ESS (numpy), and
+    with flags=True also the per-parameter BEST_ESS_* flags (int32 numpy)."""
     T = int(record.shape[0]) if n is None else int(n)
     out = np.empty(ctx.d)
-    ctx.check(_lib().best_ess(ctx.h, _tensor_ptr(record, "float32"), T, _dptr(out)))
-    return out
+    fl = np.zeros(ctx.d, dtype=np.int32)
+    ctx.check(_lib().best_ess(ctx.h, _tensor_ptr(record, "float32"), T, _dptr(out),
+                              fl.ctypes.data_as(C.c_void_p)))
+    return (out, fl) if flags else out
 
 
 def _record(rec):

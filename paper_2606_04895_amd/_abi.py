@@ -13,6 +13,7 @@ BEST_MH, BEST_MALA, BEST_HMC, BEST_AIES, BEST_NUTS, BEST_DE = range(6)
 BEST_NUTS_MAX_DEPTH = 12
 BEST_INIT_UNIFORM, BEST_INIT_REPLICATED, BEST_INIT_GAUSSIAN = range(3)
 BEST_HOST_PTRS = 1
+BEST_ESS_OK, BEST_ESS_UNTRUNCATED, BEST_ESS_FROZEN = range(3)
 
 PRECISIONS = {"fp64": BEST_FP64, "fp32": BEST_FP32, "fp16": BEST_FP16, "bf16": BEST_BF16}
 SAMPLERS = {"mh": BEST_MH, "mala": BEST_MALA, "hmc": BEST_HMC, "aies": BEST_AIES,
@@ -95,7 +96,7 @@ EXPORTS = {
     "best_set_step_multipliers": (C.c_int, [C.c_void_p, _dp]),
     "best_reinit": (C.c_int, [C.c_void_p, C.c_int32, _dp, C.c_double]),
     "best_set_mlp": (C.c_int, [C.c_void_p, _dp, C.c_double, C.c_double]),
-    "best_ess": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, _dp]),
+    "best_ess": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, _dp, C.c_void_p]),
     "best_rhat": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, _dp]),
     "best_credible": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_double, _dp,
                                 _dp, _dp, _dp, _dp, _dp, _dp]),

@@ -935,7 +935,7 @@ int best_set_mlp(best_ctx* h, const double* params, double mlp_coef, double offs
   return BEST_OK;
 }
 
-int best_ess(best_ctx* h, const float* record, int64_t T, double* ess_out) {
+int best_ess(best_ctx* h, const float* record, int64_t T, double* ess_out, int32_t* flags_out) {
   if (!h) return BEST_EINVAL;
   if (!record || !ess_out || T < 4) return fail(h, BEST_EINVAL, "record/ess_out NULL or T < 4");
   const int d = h->d;
@@ -977,9 +977,21 @@ int best_ess(best_ctx* h, const float* record, int64_t T, double* ess_out) {
     var_plus[i] = (double)(T - 1) / (double)T * w + b;
   }
   std::vector<std::vector<double>> rho(d);
-  std::vector<int> done(d, 0);
+  std::vector<int> done(d, 0), flag(d, BEST_ESS_OK);
   std::vector<double> tau(d, 1.0);
-  for (int64_t lag0 = 0; lag0 < T; lag0 += kEssLB) {
+  // every chain constant over the window: no autocorrelation estimate exists.  W = 0 up to
+  // the rounding of the chain means: W <= (1e-10 max_m |mean_m|)^2
+  for (int i = 0; i < d; ++i) {
+    double scale = 0;
+    for (int64_t c = 0; c < N; ++c) scale = std::max(scale, std::fabs(mean[i * N + c]));
+    if (!(W[i] > (1e-10 * scale) * (1e-10 * scale))) {
+      done[i] = 1;
+      flag[i] = BEST_ESS_FROZEN;
+    }
+  }
+  bool any_left = false;
+  for (int i = 0; i < d; ++i) any_left |= !done[i];
+  for (int64_t lag0 = 0; any_left && lag0 < T; lag0 += kEssLB) {
     HIPCHK(h, launch_ess_autocov(record, h->es_mean, T, d, N, lag0, h->es_part, h->stream));
     HIPCHK(h, hipMemcpyAsync(part.data(), h->es_part, part.size() * 8, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
@@ -1012,6 +1024,7 @@ int best_ess(best_ctx* h, const float* record, int64_t T, double* ess_out) {
         all = false;
         continue;
       }
+      if (!ended) flag[i] = BEST_ESS_UNTRUNCATED;
       double s = 0;
       for (size_t q = 0; q < sums.size(); ++q) {
         if (q > 0) sums[q] = std::min(sums[q], sums[q - 1]);
@@ -1023,7 +1036,10 @@ int best_ess(best_ctx* h, const float* record, int64_t T, double* ess_out) {
     }
     if (all) break;
   }
-  for (int i = 0; i < d; ++i) ess_out[i] = (double)N * (double)T / tau[i];
+  for (int i = 0; i < d; ++i) {
+    ess_out[i] = flag[i] == BEST_ESS_FROZEN ? 0.0 : (double)N * (double)T / tau[i];
+    if (flags_out) flags_out[i] = flag[i];
+  }
   return BEST_OK;
 }
 

@@ -120,20 +120,36 @@ def burn_in(ctx, sampler, warmup, d, n, n_leap=10, mh_scale=None, stretch_a=2.0,
     return time.perf_counter() - t0
 
 
+_SUMMED = ("accepted", "evals", "n_nonfinite", "n_oob", "n_recorded", "sum_accept_prob", "ms")
+
+
 def sample(ctx, sampler, steps, d, n, n_leap=10, mh_scale=None, stretch_a=2.0, ess=True,
-           max_depth=8):
-    """Timed production run with every step recorded; returns (stats, record, wall_s, ess)."""
+           max_depth=8, chunk=None, record=True):
+    """Timed production run with every step recorded; returns (stats, record, wall_s, ess).
+    chunk: launch at most this many steps per best_step call (the record continues across
+    calls and the Philox step counter makes the chains identical to one long call); the
+    count fields and the kernel time `ms` of the returned stats are summed over the calls."""
     import torch
 
     kw = dict(n_leapfrog=n_leap, stretch_a=stretch_a, max_depth=max_depth,
               mh_scale=mh_scale if mh_scale else 2.4 / np.sqrt(d))
-    rec = torch.empty((steps, d, n), dtype=torch.float32, device="cuda")
+    rec = torch.empty((steps, d, n), dtype=torch.float32, device="cuda") if record else None
+    chunk = steps if not chunk else int(chunk)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    st = best_step(ctx, sampler, steps, record=rec, **kw)
+    st = None
+    for s0 in range(0, steps, chunk):
+        k = min(chunk, steps - s0)
+        r = best_step(ctx, sampler, k, record=rec[s0:s0 + k] if rec is not None else None, **kw)
+        if st is None:
+            st = r
+        else:
+            for f in _SUMMED:
+                st[f] += r[f]
+            st["eps"], st["eps_bar"] = r["eps"], r["eps_bar"]
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    e = best_ess(ctx, rec) if ess else None
+    e = best_ess(ctx, rec) if (ess and rec is not None) else None
     return st, rec, wall, e
 
 

@@ -95,6 +95,45 @@ def test_ess_matches_oracle_on_ar1_chains():
     np.testing.assert_allclose(ess_gpu, ess_ref, rtol=1e-6)
 
 
+def _gpu_and_oracle_ess(ctx, data):
+    """data (d, n, T) -> (gpu ess, gpu flags, oracle ess, oracle flags) on the same floats."""
+    rec = torch.tensor(data.transpose(2, 0, 1).copy(), dtype=torch.float32, device="cuda")
+    e, fl = B.best_ess(ctx, rec, flags=True)
+    r32 = rec.double().cpu().numpy()
+    ref = [OE.ess_flagged(r32[:, i, :].T) for i in range(data.shape[0])]
+    return e, fl, np.array([r[0] for r in ref]), np.array([r[1] for r in ref])
+
+
+def test_ess_flags_frozen_and_untruncated_like_the_oracle():
+    """Parameter 0: chains that never move (W = 0, ESS 0, frozen); parameter 1: AR(1) with
+    coefficient 0.999 over a 50-step window (untruncated); parameter 2: AR(1) 0.3 (ok)."""
+    prob = small_problem(d=3, width=128, n_hidden=2)
+    n, T = 512, 50
+    ctx = _ctx_at_mean(prob, n)
+    rng = np.random.default_rng(17)
+    frozen = np.repeat(rng.normal(size=(n, 1)) + 3.0, T, axis=1)
+    data = np.stack([frozen, ar1_chains(rng, 0.999, n, T), ar1_chains(rng, 0.3, n, T)])
+    e, fl, e_ref, fl_ref = _gpu_and_oracle_ess(ctx, data)
+    assert list(fl) == [B.A.BEST_ESS_FROZEN, B.A.BEST_ESS_UNTRUNCATED, B.A.BEST_ESS_OK]
+    assert list(fl) == list(fl_ref)
+    assert e[0] == 0.0
+    np.testing.assert_allclose(e, e_ref, rtol=1e-6)
+
+
+def test_ess_of_a_frozen_ensemble_is_zero_not_the_window_artifact():
+    """Every chain constant over a 20-step window of 4096 chains (an ensemble that accepted
+    nothing): ESS 0 and frozen for every parameter, where the unflagged estimator gave
+    M T / (2 T - 1) = 2100.5."""
+    prob = small_problem(d=3, width=128, n_hidden=2)
+    n, T = 4096, 20
+    ctx = _ctx_at_mean(prob, n)
+    x0 = np.random.default_rng(18).normal(size=(3, n, 1))
+    data = np.repeat(x0, T, axis=2)
+    e, fl, e_ref, fl_ref = _gpu_and_oracle_ess(ctx, data)
+    assert np.all(e == 0.0) and np.all(e_ref == 0.0)
+    assert np.all(fl == B.A.BEST_ESS_FROZEN) and np.all(fl_ref == OE.FLAG_FROZEN)
+
+
 def test_ess_long_lag_extension():
     """Strongly correlated chains need lags beyond the first 128-lag pass."""
     prob = small_problem(d=3, width=128, n_hidden=2)

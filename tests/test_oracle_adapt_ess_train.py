@@ -77,6 +77,56 @@ def test_ess_of_exactly_alternating_chains_hits_the_tau_floor():
     assert ess.ess(x) == pytest.approx(M * T * np.log10(M * T), rel=1e-12)
 
 
+def test_ess_of_constant_chains_is_flagged_frozen():
+    """Chains that never move (nothing accepted): W = 0, no estimate.  Whether the chains
+    sit at one value (0/0 autocorrelations) or at different values (rho_t = 1 at every
+    lag, which used to give M T / (2 T - 1)), the ESS is 0 with the frozen flag."""
+    M, T = 4096, 20
+    same = np.full((M, T), 1.25)
+    start = np.random.default_rng(11).normal(size=(M, 1))
+    spread = np.repeat(start, T, axis=1)
+    for x in (same, spread):
+        e, flag = ess.ess_flagged(x)
+        assert e == 0.0 and flag == ess.FLAG_FROZEN
+        assert ess.ess(x) == 0.0
+    # one parameter frozen, the others not: min_ess reports 0 and names the frozen one
+    rng = np.random.default_rng(12)
+    samples = np.stack([rng.normal(size=(T, 64)), np.ones((T, 64)), rng.normal(size=(T, 64))],
+                       axis=2)
+    m, per, flags = ess.min_ess(samples)
+    assert m == 0.0 and per[1] == 0.0
+    assert list(flags) == [ess.FLAG_OK, ess.FLAG_FROZEN, ess.FLAG_OK]
+
+
+def test_ess_of_a_window_shorter_than_tau_is_flagged_untruncated():
+    """AR(1) chains with coefficient 0.999 (tau = 1999) started from their stationary law
+    and observed for 50 steps: the between-chain variance dominates var+, every pair sum the
+    window holds stays positive and the Geyer sequence is cut by the window, not by the
+    autocorrelation.  The estimate is flagged, and it is far below the M T draws."""
+    x = ar1_chains(np.random.default_rng(13), 0.999, 32, 50)
+    e, flag = ess.ess_flagged(x)
+    assert flag == ess.FLAG_UNTRUNCATED
+    assert e < 0.1 * x.size
+    # a well-mixing window of the same size ends its Geyer sequence inside the window
+    y = ar1_chains(np.random.default_rng(14), 0.3, 32, 50)
+    assert ess.ess_flagged(y)[1] == ess.FLAG_OK
+
+
+def test_cosine_learning_rate_closed_forms():
+    """lr(s) = lr1 + (lr0 - lr1)(1 + cos(pi s / S)) / 2: lr0 at s = 0, the midpoint of the
+    two rates at s = S / 2, lr1 at s = S, and a quarter of the way down at s = S / 3
+    (cos(pi / 3) = 1/2)."""
+    lr0, lr1, S = 1e-3, 1e-5, 600
+    assert train.cosine_lr(0, S, lr0, lr1) == pytest.approx(lr0, rel=1e-15)
+    assert train.cosine_lr(S // 2, S, lr0, lr1) == pytest.approx(0.5 * (lr0 + lr1), rel=1e-14)
+    assert train.cosine_lr(S, S, lr0, lr1) == pytest.approx(lr1, rel=1e-12)
+    assert train.cosine_lr(S // 3, S, lr0, lr1) == pytest.approx(lr1 + 0.75 * (lr0 - lr1),
+                                                                 rel=1e-14)
+    # monotone decreasing between the ends
+    v = [train.cosine_lr(s, S, lr0, lr1) for s in range(S + 1)]
+    assert all(a >= b for a, b in zip(v, v[1:]))
+
+
 def test_first_adam_step_closed_form():
     rng = np.random.default_rng(2)
     p = rng.normal(size=10)
