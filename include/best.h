@@ -259,6 +259,17 @@ int best_set_mlp(best_ctx *h, const double *params, double mlp_coef, double offs
 #define BEST_ESS_UNTRUNCATED 1
 #define BEST_ESS_FROZEN 2
 int best_ess(best_ctx *h, const float *record, int64_t T, double *ess_out, int32_t *flags_out);
+/* best_ess for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same estimate, bit for bit,
+ * with no hipMalloc / hipFree.  Its device scratch is one fixed array per GPU
+ * (4 * 2^20 doubles = 32 MiB, held by each GPU the library runs on until the process ends),
+ * so d * ceil(n_chains / 64) * 64 must be at most 2^20 (BEST_EINVAL otherwise, with the
+ * sizes in best_last_error).  The context's device must be current (BEST_ESTATE).  Every
+ * call on one GPU shares that GPU's array: calls that overlap on one GPU (several threads,
+ * or contexts on different streams) race and must be serialised by the caller.  Host-side
+ * working arrays of the Geyer sums are ordinary host memory.  Synchronises the stream. */
+int best_ess_noalloc(best_ctx *h, const float *record, int64_t T, double *ess_out,
+                     int32_t *flags_out);
 
 /* ---- convergence metrics (Sec. 4.1) ----
  * Samples are device records [T][d][n_chains] (floats, chain fastest), as best_step writes

@@ -20,7 +20,7 @@ __all__ = ["BestError", "Ctx", "best_init", "best_logL_grad", "best_step", "best
            "best_set_step_size", "best_set_step_multipliers", "best_reinit",
            "best_get_step_counter",
            "best_set_step_counter",
-           "best_set_mlp", "best_ess", "best_rhat", "best_credible", "best_sliced_wasserstein",
+           "best_set_mlp", "best_ess", "best_ess_noalloc", "best_rhat", "best_credible", "best_sliced_wasserstein",
            "best_mlp_nparams", "best_standardise",
            "best_importance_weights", "Trainer", "EmulatorFn"]
 
@@ -316,6 +316,17 @@ def best_ess(ctx, record, n=None, flags=False):
     fl = np.zeros(ctx.d, dtype=np.int32)
     ctx.check(_lib().best_ess(ctx.h, _tensor_ptr(record, "float32"), T, _dptr(out),
                               fl.ctypes.data_as(C.c_void_p)))
+    return (out, fl) if flags else out
+
+
+def best_ess_noalloc(ctx, record, n=None, flags=False):
+    """best_ess through the entry point that allocates no device memory (fixed per-GPU
+    scratch; d * ceil(n_chains / 64) * 64 <= 2^20)."""
+    T = int(record.shape[0]) if n is None else int(n)
+    out = np.empty(ctx.d)
+    fl = np.zeros(ctx.d, dtype=np.int32)
+    ctx.check(_lib().best_ess_noalloc(ctx.h, _tensor_ptr(record, "float32"), T, _dptr(out),
+                                      fl.ctypes.data_as(C.c_void_p)))
     return (out, fl) if flags else out
 
 

@@ -97,6 +97,7 @@ EXPORTS = {
     "best_reinit": (C.c_int, [C.c_void_p, C.c_int32, _dp, C.c_double]),
     "best_set_mlp": (C.c_int, [C.c_void_p, _dp, C.c_double, C.c_double]),
     "best_ess": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, _dp, C.c_void_p]),
+    "best_ess_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, _dp, C.c_void_p]),
     "best_rhat": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, _dp]),
     "best_credible": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_double, _dp,
                                 _dp, _dp, _dp, _dp, _dp, _dp]),

@@ -146,6 +146,9 @@ struct best_ctx {
   std::string err;
   hipStream_t stream = nullptr;
   int n_cu = 256;
+  int dev = -1;
+  double* scratch = nullptr;        // this device's fixed scratch (entry points that allocate nothing)
+  hipError_t scratch_err = hipSuccess;
   int d = 0, H = 0, nh = 0, prec = 0, MT = 1, lds_h = 0, st_lds = 0;
   int64_t N = 0, Np = 0;
   uint64_t seed = 0, step = 0;
@@ -490,6 +493,9 @@ int best_init(best_ctx** out, const best_problem* p, const best_config* c) {
     h->err = std::string("no usable HIP device: ") + hipGetErrorString(he);
     return bail(BEST_EHIP);
   }
+  h->dev = dev;
+  // the device's fixed scratch, resolved once per device with that device current
+  h->scratch_err = noalloc_scratch_address(dev, &h->scratch);
   h->d = p->d;
   h->H = p->width;
   h->nh = p->n_hidden;
@@ -935,26 +941,18 @@ int best_set_mlp(best_ctx* h, const double* params, double mlp_coef, double offs
   return BEST_OK;
 }
 
-int best_ess(best_ctx* h, const float* record, int64_t T, double* ess_out, int32_t* flags_out) {
-  if (!h) return BEST_EINVAL;
-  if (!record || !ess_out || T < 4) return fail(h, BEST_EINVAL, "record/ess_out NULL or T < 4");
+}  // extern "C"
+
+// Multi-chain ESS of a record with the given device scratch: mean and ssq [d][N], part
+// [d][ceil(N/64)][kEssLB] doubles.
+static int ess_impl(best_ctx* h, const float* record, int64_t T, double* es_mean,
+                    double* es_ssq, double* es_part, double* ess_out, int32_t* flags_out) {
   const int d = h->d;
   const int64_t N = h->N, nblk = (N + 63) / 64;
-  if (h->es_cap < N) {
-    h->mem.release(h->es_mean);
-    h->mem.release(h->es_ssq);
-    h->mem.release(h->es_part);
-    h->es_cap = 0;
-    if (h->mem.alloc(&h->es_mean, (size_t)d * N) != hipSuccess ||
-        h->mem.alloc(&h->es_ssq, (size_t)d * N) != hipSuccess ||
-        h->mem.alloc(&h->es_part, (size_t)d * nblk * kEssLB) != hipSuccess)
-      return fail(h, BEST_ENOMEM, "ESS scratch");
-    h->es_cap = N;
-  }
-  HIPCHK(h, launch_ess_chain_stats(record, T, d, N, h->es_mean, h->es_ssq, h->stream));
+  HIPCHK(h, launch_ess_chain_stats(record, T, d, N, es_mean, es_ssq, h->stream));
   std::vector<double> mean((size_t)d * N), ssq((size_t)d * N), part((size_t)d * nblk * kEssLB);
-  HIPCHK(h, hipMemcpyAsync(mean.data(), h->es_mean, mean.size() * 8, hipMemcpyDeviceToHost, h->stream));
-  HIPCHK(h, hipMemcpyAsync(ssq.data(), h->es_ssq, ssq.size() * 8, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipMemcpyAsync(mean.data(), es_mean, mean.size() * 8, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipMemcpyAsync(ssq.data(), es_ssq, ssq.size() * 8, hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
   std::vector<double> W(d), var_plus(d);
   for (int i = 0; i < d; ++i) {
@@ -992,8 +990,8 @@ int best_ess(best_ctx* h, const float* record, int64_t T, double* ess_out, int32
   bool any_left = false;
   for (int i = 0; i < d; ++i) any_left |= !done[i];
   for (int64_t lag0 = 0; any_left && lag0 < T; lag0 += kEssLB) {
-    HIPCHK(h, launch_ess_autocov(record, h->es_mean, T, d, N, lag0, h->es_part, h->stream));
-    HIPCHK(h, hipMemcpyAsync(part.data(), h->es_part, part.size() * 8, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, launch_ess_autocov(record, es_mean, T, d, N, lag0, es_part, h->stream));
+    HIPCHK(h, hipMemcpyAsync(part.data(), es_part, part.size() * 8, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
     for (int i = 0; i < d; ++i) {
       for (int t = 0; t < kEssLB && lag0 + t < T; ++t) {
@@ -1041,6 +1039,49 @@ int best_ess(best_ctx* h, const float* record, int64_t T, double* ess_out, int32
     if (flags_out) flags_out[i] = flag[i];
   }
   return BEST_OK;
+}
+
+extern "C" {
+
+int best_ess(best_ctx* h, const float* record, int64_t T, double* ess_out, int32_t* flags_out) {
+  if (!h) return BEST_EINVAL;
+  if (!record || !ess_out || T < 4) return fail(h, BEST_EINVAL, "record/ess_out NULL or T < 4");
+  const int d = h->d;
+  const int64_t N = h->N, nblk = (N + 63) / 64;
+  if (h->es_cap < N) {
+    h->mem.release(h->es_mean);
+    h->mem.release(h->es_ssq);
+    h->mem.release(h->es_part);
+    h->es_cap = 0;
+    if (h->mem.alloc(&h->es_mean, (size_t)d * N) != hipSuccess ||
+        h->mem.alloc(&h->es_ssq, (size_t)d * N) != hipSuccess ||
+        h->mem.alloc(&h->es_part, (size_t)d * nblk * kEssLB) != hipSuccess)
+      return fail(h, BEST_ENOMEM, "ESS scratch");
+    h->es_cap = N;
+  }
+  return ess_impl(h, record, T, h->es_mean, h->es_ssq, h->es_part, ess_out, flags_out);
+}
+
+int best_ess_noalloc(best_ctx* h, const float* record, int64_t T, double* ess_out,
+                     int32_t* flags_out) {
+  if (!h) return BEST_EINVAL;
+  if (!record || !ess_out || T < 4) return fail(h, BEST_EINVAL, "record/ess_out NULL or T < 4");
+  const int64_t N = h->N, nblk = (N + 63) / 64, dn = (int64_t)h->d * nblk * 64;
+  if (dn > kNoAllocMaxDN)
+    return fail(h, BEST_EINVAL, "best_ess_noalloc: d * ceil(n_chains / 64) * 64 = " +
+                                    std::to_string(dn) + " exceeds the fixed scratch limit " +
+                                    std::to_string(kNoAllocMaxDN));
+  if (!h->scratch)
+    return fail_hip(h, "best_ess_noalloc: fixed scratch address", h->scratch_err);
+  int cur = -1;
+  HIPCHK(h, hipGetDevice(&cur));
+  if (cur != h->dev) return fail(h, BEST_ESTATE, "best_ess_noalloc: the context's device is not current");
+  // carve mean [d N], ssq [d N], part [d nblk kEssLB] out of the fixed array; the kernels
+  // write every element they later read, so nothing needs clearing between calls
+  double* mean = h->scratch;
+  double* ssq = mean + dn;
+  double* part = ssq + dn;
+  return ess_impl(h, record, T, mean, ssq, part, ess_out, flags_out);
 }
 
 // ---------------------------------------------------------------------------------------

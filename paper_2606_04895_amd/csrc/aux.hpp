@@ -7,6 +7,11 @@ namespace best {
 
 constexpr int kEssTS = 64;   // time-window rows per autocovariance pass
 constexpr int kEssLB = 128;  // lags per autocovariance pass
+// Entry points that allocate nothing take their device scratch from one fixed array per
+// GPU (kernels_aux.hip).  The ESS passes need 4 d ceil(N/64) 64 doubles of it, so d times
+// the 64-padded chain count is limited to kNoAllocMaxDN (32 MiB of scratch per GPU).
+constexpr int64_t kNoAllocMaxDN = (int64_t)1 << 20;
+constexpr int64_t kNoAllocScratchDoubles = 4 * kNoAllocMaxDN;
 
 // Templated per precision (kernels_<prec>.hip).
 hipError_t launch_step(int prec, int MT, const KArgs& a, int grid, size_t lds, hipStream_t s);
@@ -33,6 +38,10 @@ hipError_t launch_moment_sums(const float* rec, const double* xs, int64_t T, int
                               double* part, int nblocks, hipStream_t s);
 hipError_t launch_ess_chain_stats(const float* rec, int64_t T, int d, int64_t N, double* mean,
                                   double* ssq, hipStream_t s);
+// Device address of GPU dev's copy of the fixed scratch array (kNoAllocScratchDoubles
+// doubles).  The first call for a device must have that device current; the address is
+// kept per device and later calls return it.
+hipError_t noalloc_scratch_address(int dev, double** p);
 hipError_t launch_ess_autocov(const float* rec, const double* mean, int64_t T, int d,
                               int64_t N, int64_t lag0, double* part, hipStream_t s);
 hipError_t launch_adam(double* p, double* m, double* v, const double* g, int64_t n, double lr,

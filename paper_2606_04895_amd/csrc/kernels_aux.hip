@@ -1,6 +1,8 @@
 // Non-templated kernels: walker initialisation, re-whitening, dual averaging, statistics,
 // ensemble moments + jittered Cholesky (Sec. 3.2), multi-chain autocovariances for ESS,
 // Adam, and the training weight-gradient GEMMs.
+#include <mutex>
+
 #include "aux.hpp"
 
 namespace best {
@@ -313,6 +315,36 @@ __global__ __launch_bounds__(kAuxThreads) void ess_autocov_kernel(const float* r
     for (int j = 0; j < 64; ++j) s += red[threadIdx.x * 64 + j];
     part[((int64_t)i * gridDim.x + blockIdx.x) * kEssLB + threadIdx.x] = s;
   }
+}
+
+// ---- fixed scratch of the entry points that allocate nothing ------------------------------
+// One copy per GPU in the code object's global segment, held until the process ends.  Host
+// code never passes this name to a kernel: the host-side symbol is not a device address.
+// Kernels get the per-device address that noalloc_scratch_address resolved.
+static __device__ __align__(256) double scratch[kNoAllocScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+double* scratch_dev[kMaxDevices] = {};
+}  // namespace
+
+hipError_t noalloc_scratch_address(int dev, double** p) {
+  *p = nullptr;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_dev[dev]) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != dev) return hipErrorInvalidDevice;  // resolved with its own device current
+    void* q = nullptr;
+    e = hipGetSymbolAddress(&q, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    scratch_dev[dev] = (double*)q;
+  }
+  *p = scratch_dev[dev];
+  return hipSuccess;
 }
 
 // ---- training: Adam on the FP64 master parameters --------------------------------------
