@@ -215,6 +215,22 @@ int best_step(best_ctx *h, int32_t sampler, int64_t n_steps, const best_step_par
  * BEST_ENOTPD the previous whitening is kept.  Also resets / finalises dual averaging. */
 int best_adapt(best_ctx *h, const best_adapt_params *p, best_adapt_info *out);
 
+/* Gradient of sum_c w_c log pi(x_c) with respect to the MLP parameters theta (the flat
+ * vector of best_problem.mlp_params): the weight gradients that training and
+ * differentiation through the emulator need (the paper relies on automatic differentiation
+ * of the emulator, Sec. 1 and Sec. 2.1).  Reverse mode through the context's network at
+ * its precision: delta_L = u_c w_out (1 - h_L^2), delta_{l-1} = (W_l^T delta_l)(1 - h_{l-1}^2)
+ * with u_c = mlp_coef w_c, then dW_l = sum_c delta_l h_{l-1}^T, db_l = sum_c delta_l,
+ * dw_out = sum_c u_c h_L, db_out = sum_c u_c (FP32 matrix cores, FP64 results).  A point
+ * whose log pi does not use the MLP (outside the training box with plain_mode 1) adds
+ * nothing; plain_mode 2 gives zeros.  The prior box is ignored (the gradient of the
+ * unbounded expression, as for best_logL_grad).  x: device [d][n]; upstream: device [n]
+ * FP64, NULL for all ones; grad_params: device FP64 [best_mlp_nparams].  Asynchronous on
+ * the context's stream.  The first call (or a larger n) allocates 2 nh width + d + 1 floats
+ * per point, n rounded up to 16 (BEST_ENOMEM).  FP64 contexts: BEST_ESTATE. */
+int best_logL_param_grad(best_ctx *h, const double *x, int64_t n, const double *upstream,
+                         double *grad_params);
+
 /* ---- state, whitening, diagnostics ---- */
 /* Checkpoint / resume.  get: x [d][n], logL [n], grad [d][n] (any may be NULL).  set: x,
  * and either both logL and grad (restored as given, so a resumed run continues bit-for-bit

@@ -20,7 +20,7 @@ __all__ = ["BestError", "Ctx", "best_init", "best_logL_grad", "best_step", "best
            "best_set_step_size", "best_set_step_multipliers", "best_reinit",
            "best_get_step_counter",
            "best_set_step_counter",
-           "best_set_mlp", "best_ess", "best_ess_noalloc", "best_rhat", "best_credible", "best_sliced_wasserstein",
+           "best_set_mlp", "best_logL_param_grad", "best_ess", "best_ess_noalloc", "best_rhat", "best_credible", "best_sliced_wasserstein",
            "best_mlp_nparams", "best_standardise",
            "best_importance_weights", "Trainer", "EmulatorFn"]
 
@@ -79,11 +79,16 @@ def _tensor_ptr(t, dtype_name):
 class Ctx:
     """Owns a best_ctx handle (best_destroy on close / garbage collection)."""
 
-    def __init__(self, handle, d, n_chains, keep):
+    def __init__(self, handle, d, n_chains, keep, width=0, n_hidden=0, mlp_coef=0.0,
+                 offset=0.0, params=None):
         self.h = handle
         self.d = d
         self.n_chains = n_chains
         self._keep = keep
+        # the network's shape and the MLP term's coefficients, as last set on the context
+        self.width, self.n_hidden = width, n_hidden
+        self.mlp_coef, self.offset = mlp_coef, offset
+        self._params = params
 
     def check(self, rc):
         if rc != A.BEST_OK:
@@ -169,7 +174,11 @@ def best_init(problem, n_chains, precision="fp32", seed=0, init="uniform", init_
     rc = lib.best_init(C.byref(h), C.byref(ps), C.byref(cfg))
     if rc != A.BEST_OK:
         raise BestError(rc, "best_init failed: " + lib.best_strerror(rc).decode())
-    return Ctx(h, int(problem["d"]), int(n_chains), None)
+    mp = problem.get("mlp_params")
+    return Ctx(h, int(problem["d"]), int(n_chains), None, width=int(problem["width"]),
+               n_hidden=int(problem["n_hidden"]), mlp_coef=float(problem.get("mlp_coef", 0.0)),
+               offset=float(problem.get("offset", 0.0)),
+               params=None if mp is None else _f64(mp).copy())
 
 
 def best_logL_grad(ctx, x, want_grad=True, out=None):
@@ -302,6 +311,22 @@ def best_set_step_multipliers(ctx, m):
 def best_set_mlp(ctx, params, mlp_coef, offset=0.0):
     p = _f64(params)
     ctx.check(_lib().best_set_mlp(ctx.h, _dptr(p), float(mlp_coef), float(offset)))
+    ctx._params, ctx.mlp_coef, ctx.offset = p.copy(), float(mlp_coef), float(offset)
+
+
+def best_logL_param_grad(ctx, x, upstream=None, out=None):
+    """Gradient of sum_c upstream[c] * log pi(x[:, c]) with respect to the flat MLP
+    parameters.  x: CUDA float64 [d][n]; upstream: CUDA float64 [n] or None (ones).
+    Returns a CUDA float64 tensor [nparams]."""
+    import torch
+    d, n = x.shape
+    npar = best_mlp_nparams(d, ctx.width, ctx.n_hidden)
+    g = torch.empty(npar, dtype=torch.float64, device=x.device) if out is None else out
+    ctx.check(_lib().best_logL_param_grad(
+        ctx.h, _tensor_ptr(x, "float64"), int(n),
+        _tensor_ptr(upstream, "float64") if upstream is not None else None,
+        _tensor_ptr(g, "float64")))
+    return g
 
 
 ESS_FLAGS = {A.BEST_ESS_OK: "ok", A.BEST_ESS_UNTRUNCATED: "untruncated",
@@ -456,20 +481,40 @@ class Trainer:
 def _emulator_fn():
     import torch
 
+    def sync_params(ctx, p):
+        """Load the MLP parameters p (float64 numpy) into the context if they differ."""
+        if ctx._params is None or ctx._params.shape != p.shape or not np.array_equal(ctx._params, p):
+            best_set_mlp(ctx, p, ctx.mlp_coef, ctx.offset)
+
     class EmulatorFn(torch.autograd.Function):
-        """log pi(x) of a context's target with the hand-written gradient as backward.
-        x: CUDA float64 tensor [d][n]; returns [n]."""
+        """log pi(x) of a context's target, differentiable with respect to the points and,
+        when given, the flat MLP parameters.  Backward runs the library's hand-written
+        kernels: the input gradient of best_logL_grad and the weight gradients of
+        best_logL_param_grad.  x: CUDA float64 [d][n]; params: float64 [nparams] (any
+        device) or None (the context's current network); returns [n]."""
 
         @staticmethod
-        def forward(fctx, ctx, x):
-            lp, g = best_logL_grad(ctx, x.detach().contiguous(), want_grad=True)
-            fctx.save_for_backward(g)
+        def forward(fctx, ctx, x, params=None):
+            p = None
+            if params is not None:
+                p = params.detach().to("cpu", torch.float64).numpy().copy()
+                sync_params(ctx, p)
+            xd = x.detach().contiguous()
+            lp, g = best_logL_grad(ctx, xd, want_grad=True)
+            fctx.ctx, fctx.p, fctx.params_like = ctx, p, params
+            fctx.save_for_backward(g, xd)
             return lp
 
         @staticmethod
         def backward(fctx, grad_out):
-            (g,) = fctx.saved_tensors
-            return None, g * grad_out[None, :]
+            g, xd = fctx.saved_tensors
+            go = grad_out.detach().to(torch.float64).contiguous()
+            gx = g * go[None, :] if fctx.needs_input_grad[1] else None
+            gp = None
+            if fctx.p is not None and fctx.needs_input_grad[2]:
+                sync_params(fctx.ctx, fctx.p)  # the network of this forward
+                gp = best_logL_param_grad(fctx.ctx, xd, go).to(fctx.params_like.device)
+            return None, gx, gp
 
     return EmulatorFn
 

@@ -83,6 +83,8 @@ EXPORTS = {
     "best_mlp_nparams": (C.c_int64, [C.c_int32, C.c_int32, C.c_int32]),
     "best_logL_grad": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
                                  C.c_uint32]),
+    "best_logL_param_grad": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
+                                       C.c_void_p]),
     "best_step": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.POINTER(StepParams),
                             C.POINTER(StepStats)]),
     "best_adapt": (C.c_int, [C.c_void_p, C.POINTER(AdaptParams), C.POINTER(AdaptInfo)]),

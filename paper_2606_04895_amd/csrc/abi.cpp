@@ -18,6 +18,7 @@ namespace best {
   hipError_t launch_step_##suf(int, const KArgs&, int, size_t, hipStream_t);                 \
   hipError_t launch_eval_##suf(int, const KArgs&, int, size_t, hipStream_t);                 \
   hipError_t launch_train_tile_##suf(int, const TrainArgs&, int, size_t, hipStream_t);       \
+  hipError_t launch_vjp_##suf(int, const VjpArgs&, int, size_t, hipStream_t);                \
   hipError_t launch_pack_##suf(const double*, int, int, int, void*, void*, void*, void*, void*, \
                                void*, hipStream_t);
 BEST_DECL_PREC(f64)
@@ -47,6 +48,14 @@ hipError_t launch_train_tile(int prec, int MT, const TrainArgs& a, int grid, siz
     case BEST_FP32: return launch_train_tile_f32(MT, a, grid, lds, s);
     case BEST_FP16: return launch_train_tile_f16(MT, a, grid, lds, s);
     case BEST_BF16: return launch_train_tile_bf16(MT, a, grid, lds, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+hipError_t launch_vjp(int prec, int MT, const VjpArgs& a, int grid, size_t lds, hipStream_t s) {
+  switch (prec) {
+    case BEST_FP32: return launch_vjp_f32(MT, a, grid, lds, s);
+    case BEST_FP16: return launch_vjp_f16(MT, a, grid, lds, s);
+    case BEST_BF16: return launch_vjp_bf16(MT, a, grid, lds, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -179,6 +188,11 @@ struct best_ctx {
   char* ev_hsave = nullptr;  // activation scratch of wider evaluation tiles
   size_t ev_hsave_bytes = 0;
   bool mult_on = false;
+  // weight-gradient (vector-Jacobian product) buffers, allocated by the first call
+  float *vj_h = nullptr, *vj_dl = nullptr, *vj_th = nullptr, *vj_up = nullptr;
+  int64_t vj_cap = 0;
+  int64_t* vj_offs = nullptr;
+  std::vector<int64_t> vj_woffs;
   NutsState nu{};
   std::vector<double> lower, upper;
   double mlp_coef = 0, offset = 0;
@@ -604,6 +618,75 @@ int best_logL_grad(best_ctx* h, const double* x, int64_t n, double* logL, double
   if (grad)
     HIPCHK(h, hipMemcpyAsync(grad, h->ev_g, nd * sizeof(double), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
+  return BEST_OK;
+}
+
+// Offsets into the flat parameter vector: [W1, b1, b2 .. b_nh, w_out, b_out] (nh + 3) and
+// the W_l blocks (l >= 2).
+static void param_offsets(int64_t d, int64_t H, int nh, std::vector<int64_t>& offs,
+                          std::vector<int64_t>& w_offs) {
+  const int64_t base = H * d + H, blk = H * H + H;
+  offs.assign(1, 0);
+  offs.push_back(H * d);
+  for (int l = 2; l <= nh; ++l) offs.push_back(base + (l - 2) * blk + H * H);
+  offs.push_back(base + (nh - 1) * blk);
+  offs.push_back(base + (nh - 1) * blk + H);
+  w_offs.clear();
+  for (int l = 2; l <= nh; ++l) w_offs.push_back(base + (l - 2) * blk);
+}
+
+int best_logL_param_grad(best_ctx* h, const double* x, int64_t n, const double* upstream,
+                         double* grad_params) {
+  if (!h) return BEST_EINVAL;
+  if (n < 0 || !grad_params || (n > 0 && !x)) return fail(h, BEST_EINVAL, "x/grad_params NULL or n < 0");
+  const int64_t np = mlp_nparams_impl(h->d, h->H, h->nh);
+  if (h->tg.plain_mode == 2 || n == 0) {
+    HIPCHK(h, hipMemsetAsync(grad_params, 0, (size_t)np * 8, h->stream));
+    return BEST_OK;
+  }
+  if (h->prec == BEST_FP64)
+    return fail(h, BEST_ESTATE, "the parameter gradient needs FP32, FP16 or BF16 precision");
+  const int64_t ldb = (n + 15) / 16 * 16;
+  if (ldb > h->vj_cap) {
+    for (void* q : {(void*)h->vj_h, (void*)h->vj_dl, (void*)h->vj_th, (void*)h->vj_up})
+      h->mem.release(q);
+    h->vj_h = h->vj_dl = h->vj_th = h->vj_up = nullptr;
+    h->vj_cap = 0;
+    const size_t rows = (size_t)h->nh * h->H;
+    if (h->mem.alloc(&h->vj_h, rows * ldb) != hipSuccess ||
+        h->mem.alloc(&h->vj_dl, rows * ldb) != hipSuccess ||
+        h->mem.alloc(&h->vj_th, (size_t)h->d * ldb) != hipSuccess ||
+        h->mem.alloc(&h->vj_up, (size_t)ldb) != hipSuccess)
+      return fail(h, BEST_ENOMEM, "parameter-gradient buffers");
+    h->vj_cap = ldb;
+  }
+  if (!h->vj_offs) {
+    std::vector<int64_t> offs;
+    param_offsets(h->d, h->H, h->nh, offs, h->vj_woffs);
+    HIPCHK(h, h->mem.upload(&h->vj_offs, offs.data(), offs.size(), h->stream));
+  }
+  VjpArgs a{};
+  a.tg = h->tg;
+  a.tg.mlp_coef = h->mlp_coef;
+  a.mp = h->mp;
+  a.lds = h->lds;
+  a.x = x;
+  a.pitch = n;
+  a.n = n;
+  a.ldb = ldb;
+  const int64_t M = 16 * h->MT;
+  a.n_tiles = (n + M - 1) / M;
+  a.upstream = upstream;
+  a.hsave = h->hsave;
+  a.hsave_stride = h->hsave_stride;
+  a.ex_h = h->vj_h;
+  a.ex_dl = h->vj_dl;
+  a.ex_th = h->vj_th;
+  a.ex_up = h->vj_up;
+  const int grid = (int)std::min<int64_t>(a.n_tiles, h->grid_cap);
+  HIPCHK(h, launch_vjp(h->prec, h->MT, a, grid, h->lds.total, h->stream));
+  HIPCHK(h, launch_dw(h->vj_dl, h->vj_h, h->vj_th, h->vj_up, ldb, h->d, h->H, h->nh,
+                      grad_params, h->vj_offs, h->vj_woffs.data(), h->stream));
   return BEST_OK;
 }
 
@@ -1510,14 +1593,8 @@ int best_trainer_create(best_trainer** out, int32_t d, int32_t width, int32_t n_
   if (t->mem.alloc((char**)&t->hsave, (size_t)t->grid_cap * t->hsave_stride * 4) != hipSuccess)
     return bail(tfail(t, BEST_ENOMEM, "activation scratch"));
   // gradient offsets: [W1, b1, b2..b_nh, w_out, b_out] and W_l (l >= 2)
-  const int64_t H = width, base = H * d + H, blk = H * H + H;
   std::vector<int64_t> offs;
-  offs.push_back(0);
-  offs.push_back(H * d);
-  for (int l = 2; l <= n_hidden; ++l) offs.push_back(base + (l - 2) * blk + H * H);
-  offs.push_back(base + (n_hidden - 1) * blk);
-  offs.push_back(base + (n_hidden - 1) * blk + H);
-  for (int l = 2; l <= n_hidden; ++l) t->w_offs.push_back(base + (l - 2) * blk);
+  param_offsets(d, width, n_hidden, offs, t->w_offs);
   if (t->mem.upload(&t->offs, offs.data(), offs.size(), t->stream) != hipSuccess)
     return bail(tfail(t, BEST_ENOMEM, "offsets"));
   if (hipError_t e = launch_pack(precision, t->p, d, width, n_hidden, t->wf, t->wb, t->w1f,

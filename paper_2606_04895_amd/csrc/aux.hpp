@@ -20,6 +20,7 @@ hipError_t launch_pack(int prec, const double* flat, int d, int H, int nh, void*
                        void* w1f, void* w1t, void* bias, void* wout, hipStream_t s);
 hipError_t launch_train_tile(int prec, int MT, const TrainArgs& a, int grid, size_t lds,
                              hipStream_t s);
+hipError_t launch_vjp(int prec, int MT, const VjpArgs& a, int grid, size_t lds, hipStream_t s);
 
 // kernels_aux.hip
 hipError_t launch_init_positions(const Target& tg, const State& S, const Rng& rng, int mode,

@@ -121,4 +121,84 @@ __global__ __launch_bounds__(kThreads, 1) void train_tile_kernel(TrainArgs a) {
   }
 }
 
+// Vector-Jacobian product of the target with respect to the MLP parameters: for points x
+// ([d][pitch] FP64) and upstream weights w_c, the tile exports what the weight-gradient GEMMs
+// need for sum_c w_c d log pi(x_c) / d theta: the normalised inputs t, the activations h_l,
+// the deltas of the reverse pass started from u_c = mlp_coef * w_c (zero for a point whose
+// log pi does not use the MLP: outside the training box with the plain fallback), and u.
+// Arrays are column-major in the point index with leading dimension ldb (n rounded up to 16);
+// the padding columns [n, ldb) are written as zeros so the GEMMs can run over ldb columns.
+struct VjpArgs {
+  Target tg;
+  MlpParams mp;
+  LdsLayout lds;
+  const double* x;
+  int64_t pitch, n, ldb, n_tiles;
+  const double* upstream;  // [n] or NULL (all ones)
+  void* hsave;
+  int64_t hsave_stride;
+  float *ex_h, *ex_dl, *ex_th, *ex_up;
+};
+
+template <class P, int MT>
+__global__ __launch_bounds__(kThreads, 1) void vjp_tile_kernel(VjpArgs a) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  using acc = typename P::acc;
+  using vec = typename P::vec;
+  using IP = typename InPrec<P>::type;
+  constexpr int M = 16 * MT;
+  const Target& tg = a.tg;
+  const int tid = local_tid(), d = a.mp.d, H = a.mp.H, nh = a.mp.nh;
+  const int K1 = a.mp.ks1 * IP::KSTEP;
+  acc* hsave = (acc*)a.hsave + (int64_t)blockIdx.x * a.hsave_stride;
+  MlpSmem<P> s = mlp_smem<P, MT>(smem + a.lds.big, a.mp);
+  s.thf = (typename IP::T*)(smem + a.lds.th);
+  s.gth = (vec*)(smem + a.lds.gth);
+  s.red = (acc*)(smem + a.lds.red);
+  s.outp = (acc*)(smem + a.lds.outp);
+  s.out = (acc*)(smem + a.lds.out);
+  s.up = (acc*)(smem + a.lds.up);
+  for (int64_t tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
+    const int64_t c0 = tile * M;
+    const int mv = (int)((a.n - c0) < M ? (a.n - c0) : M);
+    for (int e = tid; e < M * K1; e += kThreads) {
+      const int c = e / K1, i = e % K1;
+      double v = 0.0;
+      if (c < mv && i < d) {
+        v = (a.x[(int64_t)i * a.pitch + c0 + c] - tg.in_center[i]) * tg.in_invscale[i];
+        a.ex_th[(int64_t)i * a.ldb + c0 + c] = (float)v;
+      }
+      store_t<P>(s, a.mp, c, i, v);
+    }
+    for (int c = tid; c < M; c += kThreads) {
+      acc u = 0;
+      if (c < mv) {
+        bool use = tg.plain_mode == 0;
+        if (tg.plain_mode == 1) {
+          use = true;
+          for (int i = 0; i < d; ++i) {
+            const double xv = a.x[(int64_t)i * a.pitch + c0 + c];
+            use = use && xv >= tg.train_lo[i] && xv <= tg.train_hi[i];
+          }
+        }
+        const double w = a.upstream ? a.upstream[c0 + c] : 1.0;
+        u = use ? (acc)(tg.mlp_coef * w) : (acc)0;
+        a.ex_up[c0 + c] = (float)u;
+      } else if (c0 + c < a.ldb) {
+        // padding column: zero in every exported array
+        a.ex_up[c0 + c] = 0.f;
+        for (int i = 0; i < d; ++i) a.ex_th[(int64_t)i * a.ldb + c0 + c] = 0.f;
+        for (int64_t r = 0; r < (int64_t)nh * H; ++r) {
+          a.ex_h[r * a.ldb + c0 + c] = 0.f;
+          a.ex_dl[r * a.ldb + c0 + c] = 0.f;
+        }
+      }
+      s.up[c] = u;
+    }
+    MlpExport ex{a.ex_h, a.ex_dl, a.ldb, c0, mv};
+    mlp_forward<P, MT>(a.mp, s, hsave, &ex, false, true, false);
+    mlp_backward<P, MT>(a.mp, s, hsave, &ex, false, false, false);
+  }
+}
+
 }  // namespace best
