@@ -73,6 +73,11 @@ extern "C" {
 #define BEST_INIT_UNIFORM 0    /* uniform in the prior box */
 #define BEST_INIT_REPLICATED 1 /* every chain at init_point */
 #define BEST_INIT_GAUSSIAN 2   /* init_point + init_scale * L0 xi, xi ~ N(0, I) */
+#define BEST_INIT_HYPERSPHERE 3 /* the hypersphere-based perturbation of Sec. 3.2:
+                                   init_point + init_scale * L0 r u with u = xi / |xi| uniform
+                                   on the unit sphere and r = U^(1/d), i.e. uniform in the
+                                   ellipsoid of whitened radius init_scale, whose spread does
+                                   not grow with d as a Gaussian's norm (sqrt d) does */
 
 /* ---- flags for best_logL_grad / best_get_state / best_set_state ---- */
 #define BEST_HOST_PTRS 1u /* the array arguments are host pointers */
@@ -126,7 +131,7 @@ typedef struct {
   uint64_t seed;             /* Philox key */
   int32_t init;              /* BEST_INIT_* */
   const double *init_point;  /* [d] host, NULL = box centre */
-  double init_scale;         /* BEST_INIT_GAUSSIAN scale */
+  double init_scale;         /* BEST_INIT_GAUSSIAN / HYPERSPHERE scale (whitened units) */
   void *stream;              /* hipStream_t or NULL */
   int32_t chains_per_block;  /* 0 = automatic, else 16, 32 or 64 */
 } best_config;
@@ -245,11 +250,12 @@ int best_set_step_counter(best_ctx *h, uint64_t step);
 int best_set_step_size(best_ctx *h, double eps);
 /* Re-initialise every walker (Sec. 3.2 initialisation strategies, used by the burn-in loop
  * that re-centres the ensemble on its best-fit point): BEST_INIT_UNIFORM in the prior box,
- * BEST_INIT_REPLICATED at point, BEST_INIT_GAUSSIAN point + scale L xi with the CURRENT
- * whitening factor L (xi from Philox stream 4 at the current step counter, which is not
- * advanced).  point: host [d] inside the box (ignored for uniform).  log pi and its gradient
- * are re-evaluated; the whitening and step size are kept.  Gaussian draws may fall outside
- * the box (log pi = -inf there with the hard box). */
+ * BEST_INIT_REPLICATED at point, BEST_INIT_GAUSSIAN point + scale L xi and
+ * BEST_INIT_HYPERSPHERE point + scale L r u (as for best_config.init) with the CURRENT
+ * whitening factor L (xi, u, r from Philox stream 4 at the current step counter, which is
+ * not advanced).  point: host [d] inside the box (ignored for uniform).  log pi and its
+ * gradient are re-evaluated; the whitening and step size are kept.  Gaussian and
+ * hypersphere draws may fall outside the box (log pi = -inf there with the hard box). */
 int best_reinit(best_ctx *h, int32_t init, const double *point, double scale);
 /* Per-dimension step multipliers m (host [d], each finite and > 0; NULL removes them) for
  * the whitened-space MALA and MH transitions (Sec. 4.3: larger steps for chosen

@@ -110,3 +110,14 @@ def init_uniforms(seed, chains, d, step=0):
 
 def init_normals(seed, chains, d, step=0):
     return normals(seed, chains, step, STREAM_INIT, 1, d)
+
+
+def init_hypersphere(seed, chains, d, step=0):
+    """Points uniform in the unit d-ball for the hypersphere-based initialisation (Sec. 3.2):
+    u = xi / |xi| with xi the d normals of the init stream's sub 2 (uniform on the sphere,
+    Muller 1959), radius U^(1/d) with U the first uniform of block 0 of sub 3 (the ball's
+    volume below radius r is r^d).  Returns (len(chains), d)."""
+    xi = normals(seed, chains, step, STREAM_INIT, 2, d)
+    u, _ = uniforms2(seed, np.asarray(chains), step, STREAM_INIT, 3, 0)
+    r = u ** (1.0 / d)
+    return xi / np.sqrt(np.sum(xi * xi, axis=1))[:, None] * r[:, None]

@@ -25,7 +25,7 @@ __all__ = ["BestError", "Ctx", "best_init", "best_logL_grad", "best_step", "best
            "best_importance_weights", "Trainer", "EmulatorFn"]
 
 INITS = {"uniform": A.BEST_INIT_UNIFORM, "replicated": A.BEST_INIT_REPLICATED,
-         "gaussian": A.BEST_INIT_GAUSSIAN}
+         "gaussian": A.BEST_INIT_GAUSSIAN, "hypersphere": A.BEST_INIT_HYPERSPHERE}
 
 
 class BestError(RuntimeError):
@@ -293,12 +293,10 @@ def best_set_step_counter(ctx, step):
 
 
 def best_reinit(ctx, init="gaussian", point=None, scale=1.0):
-    """Re-initialise every walker (uniform / replicated / gaussian around point with the
-    current whitening factor)."""
-    modes = {"uniform": A.BEST_INIT_UNIFORM, "replicated": A.BEST_INIT_REPLICATED,
-             "gaussian": A.BEST_INIT_GAUSSIAN}
+    """Re-initialise every walker (uniform / replicated / gaussian or hypersphere around
+    point with the current whitening factor)."""
     pa = _f64(point)
-    ctx.check(_lib().best_reinit(ctx.h, modes[init] if isinstance(init, str) else int(init),
+    ctx.check(_lib().best_reinit(ctx.h, INITS[init] if isinstance(init, str) else int(init),
                                  _dptr(pa), float(scale)))
 
 

@@ -11,7 +11,7 @@ BEST_OK, BEST_EINVAL, BEST_ENOMEM, BEST_EHIP, BEST_ENOTPD, BEST_ESTATE = range(6
 BEST_FP64, BEST_FP32, BEST_FP16, BEST_BF16 = range(4)
 BEST_MH, BEST_MALA, BEST_HMC, BEST_AIES, BEST_NUTS, BEST_DE = range(6)
 BEST_NUTS_MAX_DEPTH = 12
-BEST_INIT_UNIFORM, BEST_INIT_REPLICATED, BEST_INIT_GAUSSIAN = range(3)
+BEST_INIT_UNIFORM, BEST_INIT_REPLICATED, BEST_INIT_GAUSSIAN, BEST_INIT_HYPERSPHERE = range(4)
 BEST_HOST_PTRS = 1
 BEST_ESS_OK, BEST_ESS_UNTRUNCATED, BEST_ESS_FROZEN = range(3)
 

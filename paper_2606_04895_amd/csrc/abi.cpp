@@ -369,7 +369,7 @@ static int validate_problem(best_ctx* h, const best_problem* p, const best_confi
     return fail(h, BEST_EINVAL, "n_chains must be in [1, 2^31]");
   if (c->precision < BEST_FP64 || c->precision > BEST_BF16)
     return fail(h, BEST_EINVAL, "unknown precision");
-  if (c->init < BEST_INIT_UNIFORM || c->init > BEST_INIT_GAUSSIAN)
+  if (c->init < BEST_INIT_UNIFORM || c->init > BEST_INIT_HYPERSPHERE)
     return fail(h, BEST_EINVAL, "unknown init strategy");
   if (c->chains_per_block && c->chains_per_block != 16 && c->chains_per_block != 32 &&
       c->chains_per_block != 64)
@@ -969,10 +969,10 @@ int best_set_step_size(best_ctx* h, double eps) {
 
 int best_reinit(best_ctx* h, int32_t init, const double* point, double scale) {
   if (!h) return BEST_EINVAL;
-  if (init < BEST_INIT_UNIFORM || init > BEST_INIT_GAUSSIAN)
+  if (init < BEST_INIT_UNIFORM || init > BEST_INIT_HYPERSPHERE)
     return fail(h, BEST_EINVAL, "unknown init mode");
   if (init != BEST_INIT_UNIFORM && !point) return fail(h, BEST_EINVAL, "point is NULL");
-  if (init == BEST_INIT_GAUSSIAN && !(scale >= 0 && std::isfinite(scale)))
+  if (init >= BEST_INIT_GAUSSIAN && !(scale >= 0 && std::isfinite(scale)))
     return fail(h, BEST_EINVAL, "scale must be finite and >= 0");
   const int d = h->d;
   for (int i = 0; point && i < d; ++i)

@@ -7,7 +7,7 @@
 
 namespace best {
 
-// ---- walker initialisation (Sec. 3.2: uniform / replicated / Gaussian) ----------------
+// ---- walker initialisation (Sec. 3.2: uniform / replicated / Gaussian / hypersphere) ---
 __global__ void init_positions_kernel(Target tg, State S, Rng rng, int mode, const double* pt,
                                       double scale, const double* L0, uint64_t step) {
   const int d = tg.d;
@@ -23,10 +23,22 @@ __global__ void init_positions_kernel(Target tg, State S, Rng rng, int mode, con
       v = tg.lower[i] + (tg.upper[i] - tg.lower[i]) * u;
     } else if (mode == 1) {
       v = pt[i];
-    } else {
+    } else if (mode == 2) {
       double s = 0;
       for (int j = 0; j <= i; ++j) s += L0[i * d + j] * normal_dim(rng, c, step, kStreamInit, 1, j);
       v = pt[i] + scale * s;
+    } else {
+      // uniform in the unit ball: direction xi / |xi| from d normals (sub 2), radius U^(1/d)
+      // from the first uniform of block 0 of sub 3; then mapped through L0 and scaled
+      double nn = 0, s = 0;
+      for (int j = 0; j < d; ++j) {
+        const double xj = normal_dim(rng, c, step, kStreamInit, 2, j);
+        nn += xj * xj;
+        if (j <= i) s += L0[i * d + j] * xj;
+      }
+      const U4 b = rng.block(c, step, kStreamInit, 3, 0);
+      const double r = pow(u52(b.x, b.y), 1.0 / (double)d);
+      v = pt[i] + scale * r * s / sqrt(nn);
     }
     S.x[i * S.Np + c] = v;
   }

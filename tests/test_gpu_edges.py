@@ -9,7 +9,7 @@ import torch
 
 import paper_2606_04895_amd as B
 from oracle import samplers as OS, target as OT, philox as OP
-from workloads import small_problem
+from workloads import make_problem, small_problem
 
 pytestmark = pytest.mark.gpu
 
@@ -185,8 +185,29 @@ def test_reinit_matches_the_oracle_generators():
     np.testing.assert_allclose(B.best_get_state(ctx)[0].T, ref, rtol=1e-12, atol=1e-12)
     B.best_reinit(ctx, "replicated", prob["gauss_mean"])
     assert np.array_equal(B.best_get_state(ctx)[0].T, np.tile(prob["gauss_mean"], (37, 1)))
+    B.best_reinit(ctx, "hypersphere", prob["gauss_mean"], 1.3)
+    ref = prob["gauss_mean"][None, :] + 1.3 * OP.init_hypersphere(seed, ids, 5, step=t) @ Lc.T
+    np.testing.assert_allclose(B.best_get_state(ctx)[0].T, ref, rtol=1e-12, atol=1e-12)
     with pytest.raises(B.BestError):
         B.best_reinit(ctx, "replicated", prob["upper"] + 1.0)
+    ctx.close()
+
+
+def test_hypersphere_initialisation_at_init_matches_the_oracle():
+    """best_init with the hypersphere-based initialisation (Sec. 3.2): init_point +
+    init_scale L0 r u with the initial whitening factor L0 = diag(0.1 (upper - lower)), on
+    the C5 shape (d = 27, a ragged 1000 walkers)."""
+    prob = make_problem("c5")
+    seed, n = 0xBE5C, 1000
+    pt = prob["gauss_mean"]
+    ctx = B.best_init(prob, n_chains=n, precision="bf16", seed=seed, init="hypersphere",
+                      init_point=pt, init_scale=2.0)
+    L0 = np.diag(0.1 * (prob["upper"] - prob["lower"]))
+    ref = pt[None, :] + 2.0 * OP.init_hypersphere(seed, np.arange(n, dtype=np.uint64), 27) @ L0.T
+    x = B.best_get_state(ctx)[0].T
+    np.testing.assert_allclose(x, ref, rtol=1e-12, atol=1e-12)
+    w = (x - pt) / np.diag(L0)
+    assert np.all(np.sqrt(np.sum(w * w, axis=1)) <= 2.0 + 1e-12)
     ctx.close()
 
 

@@ -71,3 +71,30 @@ def test_streams_are_distinct():
     b = ph.block(5, ids, 0, 2, 0, 0)[0]
     c = ph.block(5, ids, 1, 1, 0, 0)[0]
     assert np.mean(a == b) < 0.01 and np.mean(a == c) < 0.01
+
+
+@pytest.mark.parametrize("d", [1, 2, 6, 27])
+def test_hypersphere_points_are_uniform_in_the_unit_ball(d):
+    """Uniform in the d-ball: |u| <= 1, P(|u| <= r) = r^d (KS), mean 0 and covariance
+    I / (d + 2) (E|u|^2 = d / (d + 2)) within 5 Monte-Carlo standard errors."""
+    n = 40000
+    u = ph.init_hypersphere(123, np.arange(n), d, step=4)
+    r = np.sqrt(np.sum(u * u, axis=1))
+    assert u.shape == (n, d) and np.all(r <= 1.0)
+    assert stats.kstest(r, lambda t: np.clip(t, 0, 1) ** d).pvalue > 1e-4
+    se = np.sqrt(1.0 / (d + 2) / n)
+    assert np.all(np.abs(u.mean(0)) < 5 * se)
+    cov = u.T @ u / n
+    # Var(u_i^2) <= E u_i^4 <= 1; off-diagonal and diagonal entries within 5 SE
+    assert np.all(np.abs(cov - np.eye(d) / (d + 2)) < 5 * np.sqrt(1.0 / n))
+    if d == 2:  # a disk: a quarter of the points inside radius 1/2
+        assert abs(np.mean(r < 0.5) - 0.25) < 5 * np.sqrt(0.25 * 0.75 / n)
+
+
+def test_hypersphere_direction_and_radius_use_their_own_substreams():
+    # the direction comes from the init stream's normals of sub 2, the radius from sub 3
+    u = ph.init_hypersphere(9, np.arange(5), 4, step=2)
+    xi = ph.normals(9, np.arange(5), 2, ph.STREAM_INIT, 2, 4)
+    ua, _ = ph.uniforms2(9, np.arange(5), 2, ph.STREAM_INIT, 3, 0)
+    np.testing.assert_allclose(u, xi / np.linalg.norm(xi, axis=1)[:, None] * ua[:, None] ** 0.25,
+                               rtol=1e-14)
