@@ -355,6 +355,13 @@ const char *best_trainer_last_error(const best_trainer *t);
  * emulator then predicts log L = mean + std * MLP.  n >= 2; synchronises `stream`. */
 int best_standardise(const double *y, int64_t n, float *out, double *mean_std, void *stream);
 
+/* Normalised training inputs of the emulator: t[c][i] = (x[i][c] - center[i]) * invscale[i]
+ * (the same map best_problem.in_center / in_invscale apply before the MLP).  x: device FP64
+ * [d][n] (the library's structure-of-arrays layout); t: device FP32 [n][d] (the layout of
+ * best_train_epoch's t_in); center, invscale: host [d], finite.  Synchronises `stream`. */
+int best_normalise_inputs(const double *x, int64_t n, int32_t d, const double *center,
+                          const double *invscale, float *t, void *stream);
+
 /* Importance weights of emulator samples under the plain likelihood:
  * w_i = exp(lp_i - le_i) / sum_j exp(lp_j - le_j), evaluated with the maximum subtracted;
  * kish (host) = (sum w)^2 / sum w^2.  lp, le, w: device FP64 [n]; synchronises `stream`. */

@@ -21,7 +21,7 @@ __all__ = ["BestError", "Ctx", "best_init", "best_logL_grad", "best_step", "best
            "best_get_step_counter",
            "best_set_step_counter",
            "best_set_mlp", "best_logL_param_grad", "best_ess", "best_ess_noalloc", "best_rhat", "best_credible", "best_sliced_wasserstein",
-           "best_mlp_nparams", "best_standardise",
+           "best_mlp_nparams", "best_standardise", "best_normalise_inputs",
            "best_importance_weights", "Trainer", "EmulatorFn"]
 
 INITS = {"uniform": A.BEST_INIT_UNIFORM, "replicated": A.BEST_INIT_REPLICATED,
@@ -409,6 +409,19 @@ def best_standardise(y, stream=None):
     if rc != A.BEST_OK:
         raise BestError(rc, "best_standardise failed")
     return out, float(ms[0]), float(ms[1])
+
+
+def best_normalise_inputs(x, center, invscale, stream=None):
+    """x: CUDA float64 [d][n] -> CUDA float32 [n][d] of (x - center) * invscale."""
+    import torch
+    d, n = x.shape
+    t = torch.empty((n, d), dtype=torch.float32, device=x.device)
+    c, s = _f64(center), _f64(invscale)
+    rc = _lib().best_normalise_inputs(_tensor_ptr(x, "float64"), int(n), int(d), _dptr(c),
+                                      _dptr(s), _tensor_ptr(t, "float32"), _stream(stream))
+    if rc != A.BEST_OK:
+        raise BestError(rc, "best_normalise_inputs: " + _lib().best_strerror(rc).decode())
+    return t
 
 
 def best_importance_weights(logl_plain, logl_emu, stream=None):

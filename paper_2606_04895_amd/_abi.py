@@ -116,6 +116,8 @@ EXPORTS = {
     "best_trainer_get_params": (C.c_int, [C.c_void_p, _dp]),
     "best_trainer_last_error": (C.c_char_p, [C.c_void_p]),
     "best_standardise": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, _dp, C.c_void_p]),
+    "best_normalise_inputs": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, _dp, _dp, C.c_void_p,
+                                        C.c_void_p]),
     "best_importance_weights": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, _dp,
                                           C.c_void_p]),
 }

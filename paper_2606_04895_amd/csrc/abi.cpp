@@ -1690,6 +1690,21 @@ int best_standardise(const double* y, int64_t n, float* out, double* mean_std, v
   return (std::isfinite(mean_std[1]) && mean_std[1] > 0) ? BEST_OK : BEST_EINVAL;
 }
 
+int best_normalise_inputs(const double* x, int64_t n, int32_t d, const double* center,
+                          const double* invscale, float* t, void* stream) {
+  if (!x || !center || !invscale || !t || n < 1 || d < 1 || d > kMaxD) return BEST_EINVAL;
+  InputScaling sc{};
+  for (int i = 0; i < d; ++i) {
+    if (!std::isfinite(center[i]) || !std::isfinite(invscale[i])) return BEST_EINVAL;
+    sc.center[i] = center[i];
+    sc.invscale[i] = invscale[i];
+  }
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = launch_normalise_inputs(x, n, d, sc, t, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  return e == hipSuccess ? BEST_OK : BEST_EHIP;
+}
+
 int best_importance_weights(const double* logl_plain, const double* logl_emu, int64_t n,
                             double* w, double* kish, void* stream) {
   if (!logl_plain || !logl_emu || !w || n < 1) return BEST_EINVAL;

@@ -45,6 +45,11 @@ hipError_t launch_ess_chain_stats(const float* rec, int64_t T, int d, int64_t N,
 hipError_t noalloc_scratch_address(int dev, double** p);
 hipError_t launch_ess_autocov(const float* rec, const double* mean, int64_t T, int d,
                               int64_t N, int64_t lag0, double* part, hipStream_t s);
+struct InputScaling {  // kernel argument: per-component centre and inverse scale
+  double center[kMaxD], invscale[kMaxD];
+};
+hipError_t launch_normalise_inputs(const double* x, int64_t n, int d, const InputScaling& sc,
+                                   float* t, hipStream_t s);
 hipError_t launch_adam(double* p, double* m, double* v, const double* g, int64_t n, double lr,
                        double b1, double b2, double eps, double c1, double c2, hipStream_t s);
 hipError_t launch_dw(const float* dl, const float* h, const float* th, const float* up,

@@ -359,6 +359,18 @@ hipError_t noalloc_scratch_address(int dev, double** p) {
   return hipSuccess;
 }
 
+// ---- training inputs: t[c][i] = (x[i][c] - center[i]) invscale[i], FP64 SoA in, FP32 AoS out
+__global__ void normalise_inputs_kernel(const double* x, int64_t n, int d, InputScaling sc,
+                                        float* t) {
+  const int64_t total = (int64_t)d * n;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = e / d;
+    const int i = (int)(e % d);
+    t[e] = (float)((x[(int64_t)i * n + c] - sc.center[i]) * sc.invscale[i]);
+  }
+}
+
 // ---- training: Adam on the FP64 master parameters --------------------------------------
 __global__ void adam_kernel(double* p, double* m, double* v, const double* g, int64_t n,
                             double lr, double b1, double b2, double eps, double c1,
@@ -574,6 +586,13 @@ hipError_t launch_ess_autocov(const float* rec, const double* mean, int64_t T, i
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(ess_autocov_kernel, dim3((unsigned)((N + 63) / 64), (unsigned)d),
                      dim3(kAuxThreads), lds, s, rec, mean, T, d, N, lag0, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_normalise_inputs(const double* x, int64_t n, int d, const InputScaling& sc,
+                                   float* t, hipStream_t s) {
+  hipLaunchKernelGGL(normalise_inputs_kernel, dim3(grid_for((int64_t)d * n)), dim3(kAuxThreads),
+                     0, s, x, n, d, sc, t);
   return hipGetLastError();
 }
 

@@ -18,7 +18,8 @@ import time
 import numpy as np
 
 from . import (best_adapt, best_ess, best_get_state, best_init, best_logL_grad, best_reinit,
-               best_set_mlp, best_set_step_size, best_standardise, best_step, Trainer)
+               best_normalise_inputs, best_set_mlp, best_set_step_size, best_standardise,
+               best_step, Trainer)
 
 TARGET_ACCEPT = {"mala": 0.57, "hmc": 0.8, "nuts": 0.8}
 # Dual averaging lowers the step size without bound while nothing is accepted (chains far in
@@ -171,8 +172,7 @@ def train_emulator(prob, n_train, epochs, batch=1024, precision="fp32", seed=0,
     xt = torch.tensor(x.T.copy(), device="cuda")
     ll, _ = best_logL_grad(ctx, xt, want_grad=False)
     y, mu, sig = best_standardise(ll)
-    th = torch.tensor((x - prob["in_center"]) * prob["in_invscale"], dtype=torch.float32,
-                      device="cuda")
+    th = best_normalise_inputs(xt, prob["in_center"], prob["in_invscale"])
     t_data = time.perf_counter() - t0
     tr = Trainer(d, w, nh, xavier_mlp(rng, d, w, nh), precision=precision)
     perms = minibatch_permutations(rng, n_train, epochs)

@@ -184,6 +184,45 @@ def test_first_adam_step_matches_oracle():
     np.testing.assert_allclose(p1, ref, rtol=0, atol=1e-12)
 
 
+def test_epoch_follows_the_oracle_adam_and_cosine_schedule_step_by_step():
+    """A cosine-decayed epoch (lr0 != lr1) of 8 minibatches: every Adam step of the library
+    equals the oracle's Adam step at the oracle's cosine learning rate applied to the
+    library's gradient at that step (to FP64 rounding); one best_train_epoch call over the
+    whole epoch equals the eight one-step calls bit for bit."""
+    d, w, nh, B_, nb = 6, 128, 2, 64, 8
+    lr0, lr1 = 3e-3, 1e-4
+    rng = np.random.default_rng(12)
+    p = xavier_mlp(rng, d, w, nh)
+    th = rng.uniform(-1, 1, size=(B_ * nb, d))
+    y = rng.normal(size=B_ * nb)
+    perm = rng.permutation(B_ * nb).astype(np.int32)
+    tht = torch.tensor(th, dtype=torch.float32, device="cuda")
+    yt = torch.tensor(y, dtype=torch.float32, device="cuda")
+    ident = torch.arange(B_, dtype=torch.int32, device="cuda")
+    tr = B.Trainer(d, w, nh, p, precision="fp32")
+    opt = OTR.Adam(p.size)
+    ref = p.copy()
+    for i in range(nb):
+        idx = torch.tensor(perm[i * B_:(i + 1) * B_].astype(np.int64), device="cuda")
+        tb, yb = tht[idx].contiguous(), yt[idx].contiguous()
+        _, g = tr.grad(tb, yb)
+        tr.epoch(tb, yb, ident, B_, lr0, lr1, i, nb)
+        ref = opt.step(ref, g, OTR.cosine_lr(i, nb, lr0, lr1))
+        np.testing.assert_allclose(tr.params(), ref, rtol=0, atol=1e-12)
+    tr2 = B.Trainer(d, w, nh, p, precision="fp32")
+    tr2.epoch(tht, yt, torch.tensor(perm, device="cuda"), B_, lr0, lr1, 0, nb)
+    assert np.array_equal(tr2.params(), tr.params())
+
+
+def test_normalise_inputs_matches_the_oracle_map():
+    prob = make_problem("c4")
+    rng = np.random.default_rng(13)
+    x = prob["lower"] + rng.uniform(size=(1000, 6)) * (prob["upper"] - prob["lower"])
+    t = B.best_normalise_inputs(torch.tensor(x.T.copy(), device="cuda"), prob["in_center"],
+                                prob["in_invscale"]).cpu().numpy()
+    assert np.array_equal(t, OT.normalise(prob, x).astype(np.float32))
+
+
 def test_training_reduces_loss_on_plain_model_pairs():
     prob = make_problem("c4")
     n = 4096
