@@ -81,6 +81,8 @@ extern "C" {
 
 /* ---- flags for best_logL_grad / best_get_state / best_set_state ---- */
 #define BEST_HOST_PTRS 1u /* the array arguments are host pointers */
+#define BEST_AOS 2u       /* best_logL_grad: x and grad are point-major [n][d] (element
+                             (c, i) at c * d + i) instead of structure-of-arrays */
 
 typedef struct best_ctx best_ctx;
 typedef struct best_trainer best_trainer;
@@ -197,10 +199,14 @@ int64_t best_mlp_nparams(int32_t d, int32_t width, int32_t n_hidden);
 
 /* ---- the hot path ---- */
 
-/* Batch evaluation of log pi(x) and grad_x log pi(x) at n points x ([d][n]).  grad may be
- * NULL (logL only).  Device pointers, or host pointers with BEST_HOST_PTRS (then the call
- * synchronises).  The prior box applies: -inf outside (the gradient returned there is that
- * of the unbounded expression), or the smooth penalty with box_penalty = 1. */
+/* Batch evaluation of log pi(x) and grad_x log pi(x) at n points x: the emulator evaluated
+ * for many walkers at once, whose cost stays flat in the batch size up to the device's
+ * width (Sec. 2.3 and Fig. 1), with the gradient the samplers of Sec. 2.1 need.  x and grad
+ * are [d][n] (structure-of-arrays), or [n][d] with BEST_AOS (converted on the device through
+ * a library scratch of 2 d n + n doubles, allocated by the first such call or a larger n).
+ * grad may be NULL (logL only).  Device pointers, or host pointers with BEST_HOST_PTRS (then
+ * the call synchronises).  The prior box applies: -inf outside (the gradient returned there
+ * is that of the unbounded expression), or the smooth penalty with box_penalty = 1. */
 int best_logL_grad(best_ctx *h, const double *x, int64_t n, double *logL, double *grad,
                    uint32_t flags);
 

@@ -181,28 +181,30 @@ def best_init(problem, n_chains, precision="fp32", seed=0, init="uniform", init_
                params=None if mp is None else _f64(mp).copy())
 
 
-def best_logL_grad(ctx, x, want_grad=True, out=None):
-    """x: [d][n] float64 (numpy -> host path, torch CUDA tensor -> device path).
-    Returns (logL, grad) of the same kind (grad None if not wanted)."""
+def best_logL_grad(ctx, x, want_grad=True, out=None, aos=False):
+    """x: [d][n] float64, or [n][d] with aos=True (numpy -> host path, torch CUDA tensor ->
+    device path).  Returns (logL, grad) of the same kind and layout (grad None if not
+    wanted)."""
     lib = _lib()
+    flags = A.BEST_AOS if aos else 0
     if _is_tensor(x):
         import torch
-        d, n = x.shape
+        n = x.shape[0] if aos else x.shape[1]
         lp = torch.empty(n, dtype=torch.float64, device=x.device) if out is None else out[0]
-        g = (torch.empty((d, n), dtype=torch.float64, device=x.device) if out is None else out[1]) \
-            if want_grad else None
+        g = (torch.empty(tuple(x.shape), dtype=torch.float64, device=x.device) if out is None
+             else out[1]) if want_grad else None
         ctx.check(lib.best_logL_grad(ctx.h, _tensor_ptr(x, "float64"), n,
                                      _tensor_ptr(lp, "float64"),
-                                     _tensor_ptr(g, "float64") if g is not None else None, 0))
+                                     _tensor_ptr(g, "float64") if g is not None else None, flags))
         return lp, g
     xa = _f64(x)
-    d, n = xa.shape
+    n = xa.shape[0] if aos else xa.shape[1]
     lp = np.empty(n)
-    g = np.empty((d, n)) if want_grad else None
+    g = np.empty(xa.shape) if want_grad else None
     ctx.check(lib.best_logL_grad(ctx.h, xa.ctypes.data_as(C.c_void_p), n,
                                  lp.ctypes.data_as(C.c_void_p),
                                  g.ctypes.data_as(C.c_void_p) if g is not None else None,
-                                 A.BEST_HOST_PTRS))
+                                 flags | A.BEST_HOST_PTRS))
     return lp, g
 
 

@@ -13,6 +13,7 @@ BEST_MH, BEST_MALA, BEST_HMC, BEST_AIES, BEST_NUTS, BEST_DE = range(6)
 BEST_NUTS_MAX_DEPTH = 12
 BEST_INIT_UNIFORM, BEST_INIT_REPLICATED, BEST_INIT_GAUSSIAN, BEST_INIT_HYPERSPHERE = range(4)
 BEST_HOST_PTRS = 1
+BEST_AOS = 2
 BEST_ESS_OK, BEST_ESS_UNTRUNCATED, BEST_ESS_FROZEN = range(3)
 
 PRECISIONS = {"fp64": BEST_FP64, "fp32": BEST_FP32, "fp16": BEST_FP16, "bf16": BEST_BF16}

@@ -607,17 +607,42 @@ int best_logL_grad(best_ctx* h, const double* x, int64_t n, double* logL, double
   if (!h) return BEST_EINVAL;
   if (n < 0 || (n > 0 && (!x || !logL))) return fail(h, BEST_EINVAL, "x/logL NULL or n < 0");
   if (n == 0) return BEST_OK;
-  if (flags & ~BEST_HOST_PTRS) return fail(h, BEST_EINVAL, "unknown flags");
-  if (!(flags & BEST_HOST_PTRS)) return run_eval(h, x, n, n, logL, grad);
+  if (flags & ~(BEST_HOST_PTRS | BEST_AOS)) return fail(h, BEST_EINVAL, "unknown flags");
+  const bool aos = (flags & BEST_AOS) != 0;
+  const int64_t d = h->d;
+  const size_t nd = (size_t)n * d;
+  if (!(flags & BEST_HOST_PTRS)) {
+    if (!aos) return run_eval(h, x, n, n, logL, grad);
+    // point-major [n][d] device arrays: through the structure-of-arrays scratch
+    int rc = ensure_eval_scratch(h, n);
+    if (rc) return rc;
+    HIPCHK(h, launch_transpose(x, n, d, h->ev_x, h->stream));
+    if ((rc = run_eval(h, h->ev_x, n, n, logL, grad ? h->ev_g : nullptr))) return rc;
+    if (grad) HIPCHK(h, launch_transpose(h->ev_g, d, n, grad, h->stream));
+    return BEST_OK;
+  }
   int rc = ensure_eval_scratch(h, n);
   if (rc) return rc;
-  const size_t nd = (size_t)n * h->d;
-  HIPCHK(h, hipMemcpyAsync(h->ev_x, x, nd * sizeof(double), hipMemcpyHostToDevice, h->stream));
+  std::vector<double> tmp;
+  const double* xs = x;
+  if (aos) {  // host point-major input: reorder on the host
+    tmp.resize(nd);
+    for (int64_t c = 0; c < n; ++c)
+      for (int64_t i = 0; i < d; ++i) tmp[i * n + c] = x[c * d + i];
+    xs = tmp.data();
+  }
+  HIPCHK(h, hipMemcpyAsync(h->ev_x, xs, nd * sizeof(double), hipMemcpyHostToDevice, h->stream));
   if ((rc = run_eval(h, h->ev_x, n, n, h->ev_lp, grad ? h->ev_g : nullptr))) return rc;
   HIPCHK(h, hipMemcpyAsync(logL, h->ev_lp, n * sizeof(double), hipMemcpyDeviceToHost, h->stream));
-  if (grad)
-    HIPCHK(h, hipMemcpyAsync(grad, h->ev_g, nd * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  if (grad) {
+    if (aos) tmp.resize(nd);
+    HIPCHK(h, hipMemcpyAsync(aos ? tmp.data() : grad, h->ev_g, nd * sizeof(double),
+                             hipMemcpyDeviceToHost, h->stream));
+  }
   HIPCHK(h, hipStreamSynchronize(h->stream));
+  if (grad && aos)
+    for (int64_t c = 0; c < n; ++c)
+      for (int64_t i = 0; i < d; ++i) grad[c * d + i] = tmp[i * n + c];
   return BEST_OK;
 }
 

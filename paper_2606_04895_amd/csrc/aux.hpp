@@ -45,6 +45,8 @@ hipError_t launch_ess_chain_stats(const float* rec, int64_t T, int d, int64_t N,
 hipError_t noalloc_scratch_address(int dev, double** p);
 hipError_t launch_ess_autocov(const float* rec, const double* mean, int64_t T, int d,
                               int64_t N, int64_t lag0, double* part, hipStream_t s);
+hipError_t launch_transpose(const double* src, int64_t rows, int64_t cols, double* dst,
+                            hipStream_t s);
 struct InputScaling {  // kernel argument: per-component centre and inverse scale
   double center[kMaxD], invscale[kMaxD];
 };

@@ -359,6 +359,16 @@ hipError_t noalloc_scratch_address(int dev, double** p) {
   return hipSuccess;
 }
 
+// ---- layout conversion: dst[j][i] = src[i][j] for a rows x cols row-major source ----------
+__global__ void transpose_kernel(const double* src, int64_t rows, int64_t cols, double* dst) {
+  const int64_t total = rows * cols;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / cols, j = e % cols;
+    dst[j * rows + i] = src[e];
+  }
+}
+
 // ---- training inputs: t[c][i] = (x[i][c] - center[i]) invscale[i], FP64 SoA in, FP32 AoS out
 __global__ void normalise_inputs_kernel(const double* x, int64_t n, int d, InputScaling sc,
                                         float* t) {
@@ -586,6 +596,13 @@ hipError_t launch_ess_autocov(const float* rec, const double* mean, int64_t T, i
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(ess_autocov_kernel, dim3((unsigned)((N + 63) / 64), (unsigned)d),
                      dim3(kAuxThreads), lds, s, rec, mean, T, d, N, lag0, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_transpose(const double* src, int64_t rows, int64_t cols, double* dst,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(transpose_kernel, dim3(grid_for(rows * cols)), dim3(kAuxThreads), 0, s, src,
+                     rows, cols, dst);
   return hipGetLastError();
 }
 

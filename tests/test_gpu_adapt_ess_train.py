@@ -77,9 +77,12 @@ def test_dual_averaging_reaches_target_acceptance(sampler, target):
     B.best_adapt(ctx, update_mean=False, finalize_da=True)
     st = B.best_step(ctx, sampler, 150, n_leapfrog=10)
     acc = st["accepted"] / (150 * 2048)
+    print(f"dual averaging {sampler}: acceptance {acc:.4f} at eps {st['eps']:.4g} "
+          f"(target {target})", flush=True)
     # the averaged iterate of dual averaging sits slightly off the target where the
-    # acceptance curve bends; 0.08 covers that bias and the Monte-Carlo noise
-    assert abs(acc - target) < 0.08, (sampler, acc, st["eps"])
+    # acceptance curve bends (measured 0.007 for MALA, 0.009 for HMC on this workload; the
+    # Monte-Carlo error of the mean over 2048 x 150 draws is about 0.002): 0.03 bounds both
+    assert abs(acc - target) < 0.03, (sampler, acc, st["eps"])
 
 
 def test_ess_matches_oracle_on_ar1_chains():

@@ -278,3 +278,18 @@ def test_nonfinite_weights_are_rejected_and_counted():
     ctx = B.best_init(prob, n_chains=32, precision="fp32", seed=1)
     with pytest.raises(B.BestError):
         B.best_set_mlp(ctx, p, 0.5)
+
+
+def test_logL_grad_point_major_layout():
+    """BEST_AOS: [n][d] points and gradients, device and host pointers, equal to the
+    structure-of-arrays call element for element (a ragged 333 points on C2)."""
+    prob = make_problem("c2")
+    ctx = B.best_init(prob, n_chains=64, precision="fp32", seed=2)
+    x = _points(prob, 333, 21)
+    lp0, g0 = B.best_logL_grad(ctx, torch.tensor(x.T.copy(), device="cuda"))
+    lp1, g1 = B.best_logL_grad(ctx, torch.tensor(x, device="cuda"), aos=True)
+    assert torch.equal(lp0, lp1) and torch.equal(g0.T, g1)
+    lp2, g2 = B.best_logL_grad(ctx, x, aos=True)
+    assert np.array_equal(lp2, lp0.cpu().numpy()) and np.array_equal(g2, g1.cpu().numpy())
+    lp3, _ = B.best_logL_grad(ctx, torch.tensor(x, device="cuda"), want_grad=False, aos=True)
+    torch.testing.assert_close(lp3, lp0, rtol=1e-12, atol=1e-12)
