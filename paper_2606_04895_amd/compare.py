@@ -98,10 +98,11 @@ def main():
         tail = rec[-args.sw_steps:].contiguous()
         del rec
         if k == 0:
-            flat = keep.double().permute(0, 2, 1).reshape(-1, d)
-            mu = flat.mean(0).cpu().numpy()
-            L = np.linalg.cholesky(torch.cov(flat.T).cpu().numpy())
-            del flat
+            # the reference whitening from the library's own moments and Cholesky (the
+            # adaptation path), over the retained half of the run; the run is finished, so
+            # its context's whitening may change
+            B.best_adapt(ctx, samples=keep, update_mean=True)
+            mu, L = B.best_get_whitening(ctx)
             ref.update(W=(mu, L), tail=tail, ctx=ctx,
                        lim={a: B.best_credible(ctx, keep, a, whitening=(mu, L))[:2]
                             for a in (0.68, 0.95)})

@@ -110,6 +110,10 @@ def test_twisted_pair_has_closed_form_moments():
     xv = prob["gauss_mean"][tw["v"]] + sig_w * rng.normal(size=n) - tw["beta"] * (
         (xu - tw["center"]) ** 2 - tw["kappa"])
     assert abs(np.var(xv) / prob["closed_cov"][tw["v"], tw["v"]] - 1) < 0.02
+    # the Gaussian block: its closed-form covariance inverts its precision block
+    gi = [i for i in range(prob["d"]) if i not in (tw["u"], tw["v"])]
+    np.testing.assert_allclose(prob["closed_cov"][np.ix_(gi, gi)] @ prob["gauss_prec"][np.ix_(gi, gi)],
+                               np.eye(len(gi)), atol=1e-10)
     x = np.tile(prob["gauss_mean"], (1, 1))
     x[0, tw["u"]] = tw["center"]
     x[0, tw["v"]] = prob["gauss_mean"][tw["v"]] + tw["beta"] * tw["kappa"]

@@ -236,6 +236,9 @@ def small_problem(d=5, width=64, n_hidden=3, seed=7, twist=False, with_mlp=True)
         prec[u, u] = 1.0 / sig_u ** 2
         prec[v, v] = 1.0 / sig_w ** 2
         beta = 100.0 * b_lat * sig_w / sig_u ** 2
+        # the Gaussian block's covariance is the inverse of its (kept) precision block
+        g = [i for i in range(d) if i not in (u, v)]
+        cov[np.ix_(g, g)] = np.linalg.inv(prec[np.ix_(g, g)])
         cov[u, u] = sig_u ** 2
         cov[v, v] = sig_w ** 2 + 2.0 * beta ** 2 * sig_u ** 4
         tw = dict(u=u, v=v, beta=beta, center=float(mu[u]), kappa=sig_u ** 2)
