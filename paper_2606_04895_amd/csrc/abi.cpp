@@ -115,17 +115,19 @@ int in_size(int prec) { return prec == BEST_FP64 ? 8 : 4; }
 int in_ksteps(int prec, int d) { return (d + in_kstep(prec) - 1) / in_kstep(prec); }
 int grad_rtiles(int d) { return (d + 15) / 16; }
 
-LdsLayout layout_for(int prec, int MT, int H, int d, int nh, int lds_h, int st_lds = 0) {
-  return lds_layout(16 * MT, H, d, nh, lds_h, tsize(prec), vasize(prec), vasize(prec),
-                    in_ksteps(prec, d) * in_kstep(prec), in_size(prec), tile_waves(tsize(prec)),
-                    st_lds);
-}
-
 // Packed input-layer weights: W_1 for the input GEMM and W_1^T for the input gradient.
 size_t w1f_bytes(int prec, int H, int d) {
   return (size_t)H * in_ksteps(prec, d) * in_kstep(prec) * in_size(prec);
 }
 size_t w1t_bytes(int prec, int H, int d) { return (size_t)16 * grad_rtiles(d) * H * tsize(prec); }
+
+LdsLayout layout_for(int prec, int MT, int H, int d, int nh, int lds_h, int st_lds = 0,
+                     int w1_res = 0) {
+  return lds_layout(16 * MT, H, d, nh, lds_h, tsize(prec), vasize(prec), vasize(prec),
+                    in_ksteps(prec, d) * in_kstep(prec), in_size(prec), tile_waves(tsize(prec)),
+                    st_lds, w1_res ? (int)w1f_bytes(prec, H, d) : 0,
+                    w1_res ? (int)w1t_bytes(prec, H, d) : 0);
+}
 
 MlpParams make_mlp_params(int prec, int d, int H, int nh, int lds_h, void* wf, void* wb,
                           void* w1f, void* w1t, void* bias, void* wout) {
@@ -158,7 +160,7 @@ struct best_ctx {
   int dev = -1;
   double* scratch = nullptr;        // this device's fixed scratch (entry points that allocate nothing)
   hipError_t scratch_err = hipSuccess;
-  int d = 0, H = 0, nh = 0, prec = 0, MT = 1, lds_h = 0, st_lds = 0;
+  int d = 0, H = 0, nh = 0, prec = 0, MT = 1, lds_h = 0, st_lds = 0, w1_lds = 0;
   int64_t N = 0, Np = 0;
   uint64_t seed = 0, step = 0;
   Arena mem;
@@ -404,8 +406,13 @@ static int choose_mt(best_ctx* h, const best_config* c) {
   h->MT = mt;
   h->mt_fixed = c->chains_per_block != 0;
   h->lds_h = fits(mt, 1) ? 1 : 0;
-  // the sampler's per-step FP64 scratch goes to LDS too when there is room
+  // the sampler's per-step FP64 scratch goes to LDS too when there is room, and then the
+  // input layer's weights (W_1, W_1^T), which every evaluation reads
   h->st_lds = layout_for(h->prec, mt, h->H, h->d, h->nh, h->lds_h, 1).total <= kLdsMax ? 1 : 0;
+  // (never at the cost of a second workgroup per CU)
+  const int base = layout_for(h->prec, mt, h->H, h->d, h->nh, h->lds_h, h->st_lds).total;
+  const int with = layout_for(h->prec, mt, h->H, h->d, h->nh, h->lds_h, h->st_lds, 1).total;
+  h->w1_lds = with <= kLdsMax && (2 * base > kLdsMax || 2 * with <= kLdsMax) ? 1 : 0;
   return BEST_OK;
 }
 
@@ -518,7 +525,7 @@ int best_init(best_ctx** out, const best_problem* p, const best_config* c) {
   h->Np = (h->N + 63) / 64 * 64;
   h->seed = c->seed;
   if ((rc = choose_mt(h, c))) return bail(rc);
-  h->lds = layout_for(h->prec, h->MT, h->H, h->d, h->nh, h->lds_h, h->st_lds);
+  h->lds = layout_for(h->prec, h->MT, h->H, h->d, h->nh, h->lds_h, h->st_lds, h->w1_lds);
   if ((rc = upload_problem(h, p))) return bail(rc);
   if ((rc = alloc_mlp(h))) return bail(rc);
   if (p->plain_mode != 2) {

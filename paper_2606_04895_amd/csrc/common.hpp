@@ -16,7 +16,10 @@ namespace best {
 // whose L2 weight stream needs the extra waves in flight, 4 (one per SIMD, the whole
 // register file each) for FP32 and FP64.  Each precision's translation unit sets
 // BEST_WAVES from this rule; the host sizes LDS with the same rule.
-constexpr int tile_waves(int elem_bytes) { return elem_bytes == 2 ? 8 : 4; }
+#ifndef BEST_WAVES16
+#define BEST_WAVES16 8
+#endif
+constexpr int tile_waves(int elem_bytes) { return elem_bytes == 2 ? BEST_WAVES16 : 4; }
 #ifndef BEST_WAVES
 #define BEST_WAVES 4
 #endif

@@ -72,7 +72,8 @@ struct NutsState {
 
 // Byte offsets into dynamic LDS (computed on the host by lds_layout()).
 struct LdsLayout {
-  int big, th, gth, red, outp, out, up, mi, md, st, cst, total;
+  int big, th, gth, red, outp, out, up, mi, md, st, cst, w1, total;
+  int w1f_bytes, w1t_bytes;  // sizes of the resident input-layer weights (w1 >= 0)
 };
 
 __host__ __device__ inline int align16(int v) { return (v + 15) & ~15; }
@@ -83,10 +84,12 @@ __host__ __device__ inline int align16(int v) { return (v + 15) & ~15; }
 // k-step); waves is the tile workgroup's wave count (per-wave partial sums).
 // With st_lds the per-step FP64 scratch of the tile (7 [d][M] arrays and log pi of the
 // proposals) and the launch's small constant arrays also live in LDS (st, cst >= 0), else
-// they stay in global memory (-1).
+// they stay in global memory (-1).  With w1_bytes = (w1f, w1t) sizes > 0 the input layer's
+// packed weights W_1 and W_1^T are copied into LDS once per launch (w1 >= 0).
 __host__ __device__ inline LdsLayout lds_layout(int M, int H, int d, int nh, int lds_h,
                                                int tsize, int vsize, int asize, int k1,
-                                               int isize, int waves, int st_lds) {
+                                               int isize, int waves, int st_lds,
+                                               int w1f_bytes = 0, int w1t_bytes = 0) {
   LdsLayout L;
   const int mlp_bytes = (lds_h ? nh + 2 : 2) * M * H * tsize;
   const int asm_bytes = 8 * (2 * d * M + M + M * d + kMaxD + 3 * kMaxTerms + waves * 32);
@@ -123,6 +126,14 @@ __host__ __device__ inline LdsLayout lds_layout(int M, int H, int d, int nh, int
     o = align16(o + (7 * d * M + M) * 8);
     L.cst = o;  // launch constants: L, S^-1 (d x d), mu, gauss mean, box, input scaling
     o = align16(o + (2 * d * d + 8 * d) * 8);
+  }
+  L.w1 = -1;
+  L.w1f_bytes = L.w1t_bytes = 0;
+  if (w1f_bytes > 0) {
+    L.w1 = o;
+    L.w1f_bytes = w1f_bytes;
+    L.w1t_bytes = w1t_bytes;
+    o = align16(o + w1f_bytes + w1t_bytes);
   }
   L.total = o;
   return L;
@@ -1048,6 +1059,20 @@ __device__ __forceinline__ void de_tile(const KArgs& a, char* smem, typename P::
 // into LDS and point the kernel's argument copy at them; they are read in every phase of
 // every step.
 __device__ __forceinline__ void stage_constants(KArgs& a, char* smem) {
+  if (a.lds.w1 >= 0) {
+    // the input layer's packed weights (read by every evaluation of the launch)
+    typedef int i4 __attribute__((ext_vector_type(4)));
+    const int nf = a.lds.w1f_bytes / 16, nt = a.lds.w1t_bytes / 16;
+    const i4* __restrict__ sf = (const i4*)a.mp.w1f;
+    const i4* __restrict__ st = (const i4*)a.mp.w1t;
+    i4* df = (i4*)(smem + a.lds.w1);
+    i4* dt = df + nf;
+    for (int e = local_tid(); e < nf; e += kThreads) df[e] = sf[e];
+    for (int e = local_tid(); e < nt; e += kThreads) dt[e] = st[e];
+    a.mp.w1f = df;
+    a.mp.w1t = dt;
+    if (a.lds.cst < 0) __syncthreads();
+  }
   if (a.lds.cst < 0) return;
   const int d = a.tg.d, dd = d * d, tid = local_tid();
   double* c = (double*)(smem + a.lds.cst);

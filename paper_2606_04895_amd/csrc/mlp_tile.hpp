@@ -32,6 +32,15 @@ namespace best {
 #define BEST_PREFETCH 4
 #endif
 constexpr int kPrefetch = BEST_PREFETCH;  // k-steps of weight fragments in flight per wave
+// Wider chain tiles issue MT MFMAs per weight fragment, so a shallower ring keeps the stream
+// fed and leaves the registers to the MT accumulators and activation fragments.
+#ifndef BEST_PREFETCH_WIDE
+#define BEST_PREFETCH_WIDE 4
+#endif
+template <int MT>
+constexpr int prefetch_depth() {
+  return MT >= 2 ? BEST_PREFETCH_WIDE : kPrefetch;
+}
 // Row tiles per register group: 4 with a whole register file per wave, 2 when two waves
 // share a SIMD.
 #ifndef BEST_RG_MAX
@@ -132,7 +141,7 @@ __device__ __forceinline__ void gemm_pass_rg(int n_layers, int KS, int rtw0, int
   using frag = typename P::frag;
   using accv = typename P::accv;
   using acc = typename P::acc;
-  constexpr int D = kPrefetch;
+  constexpr int D = prefetch_depth<MT>();
   const int lane = local_tid() & 63;
   const int ng = RTW / RG;
   frag a[D][RG];
