@@ -54,11 +54,11 @@ def main():
 
     prob = make_problem(args.config)
     d, n = prob["d"], args.chains
-    plan = {  # (warm-up steps, production steps)
+    plan = {  # (warm-up steps, production steps): the same lengths for every sampler
         "aies": (2000, 2000),
-        "mala": (1000, 2000),
-        "hmc": (1000, 1000),
-        "nuts": (400, 300),
+        "mala": (2000, 2000),
+        "hmc": (2000, 2000),
+        "nuts": (2000, 2000),
     }
     if args.quick:
         plan = {k: (max(50, w // 10), max(50, s // 10)) for k, (w, s) in plan.items()}
@@ -73,8 +73,10 @@ def main():
         ctx = B.best_init(prob, n_chains=n, precision=args.precision, seed=seed, init="uniform")
         t_burn = driver.burn_in(ctx, sampler, warm, d, n, max_depth=args.max_depth,
                                 recenter=args.recenter)
-        st, rec, wall, ess = driver.sample(ctx, sampler, steps, d, n, max_depth=args.max_depth)
-        return ctx, st, rec, wall, ess, t_burn
+        st, rec, wall, _ = driver.sample(ctx, sampler, steps, d, n, max_depth=args.max_depth,
+                                         ess=False)
+        ess, flags = B.best_ess(ctx, rec, flags=True)
+        return ctx, st, rec, wall, (ess, flags), t_burn
 
     # reference posterior: two independent long MALA runs (the second sets the noise floor of
     # the credible metric and the sliced Wasserstein distance, as in Sec. 4.1)
@@ -110,7 +112,7 @@ def main():
             floor = metrics(ctx, keep, tail)
             emit(dict(kind="metric_reference_pair", config=args.config, reference="mala",
                       chains=n, warmup=ref_warm, steps=ref_steps, sw_draws=args.sw_steps * n,
-                      min_ess=float(ess.min()), **floor))
+                      min_ess=float(ess[0].min()), **floor))
             ctx.close()
         del keep
         torch.cuda.synchronize()
@@ -120,10 +122,18 @@ def main():
         prod = rec[steps // 2:].contiguous()
         m = metrics(ctx, prod, rec[-args.sw_steps:].contiguous())
         del prod
+        ess, flags = ess
+        # a min-ESS/s only for a converged run: no flagged ESS and R - 1 below 0.1
+        reason = None
+        if any(int(f) != B.A.BEST_ESS_OK for f in flags):
+            reason = "ESS flagged: " + ",".join(sorted({B.ESS_FLAGS[int(f)] for f in flags}))
+        elif not m["rminus1"] < 0.1:
+            reason = f"not converged: R - 1 = {m['rminus1']:.3g}"
         row = dict(kind="sampler_comparison", config=args.config, precision=args.precision,
                    sampler=sampler, chains=n, d=d, warmup=warm, steps=steps,
                    burn_in_s=t_burn, production_s=wall, min_ess=float(ess.min()),
-                   min_ess_per_s=float(ess.min()) / wall, evals=int(st["evals"]),
+                   min_ess_per_s=None if reason else float(ess.min()) / wall,
+                   min_ess_null_reason=reason, evals=int(st["evals"]),
                    evals_per_s=st["evals"] / wall,
                    accept=st["sum_accept_prob"] / (steps * n), eps=st["eps"], **m)
         del rec
