@@ -48,7 +48,7 @@ struct Prec<__bf16> {
   using accv = f32x4;
   static constexpr int EPL = 8, KSTEP = 32;
   static constexpr bool ROWS4 = true;  // D slots r = 0..3 hold rows 4g .. 4g + 3
-  __device__ static constexpr int drow(int g, int r) { return 4 * g + r; }
+  __host__ __device__ static constexpr int drow(int g, int r) { return 4 * g + r; }
   __device__ static accv mma(frag a, frag b, accv c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
   }
@@ -63,7 +63,7 @@ struct Prec<_Float16> {
   using accv = f32x4;
   static constexpr int EPL = 8, KSTEP = 32;
   static constexpr bool ROWS4 = true;
-  __device__ static constexpr int drow(int g, int r) { return 4 * g + r; }
+  __host__ __device__ static constexpr int drow(int g, int r) { return 4 * g + r; }
   __device__ static accv mma(frag a, frag b, accv c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
   }
@@ -78,7 +78,7 @@ struct Prec<float> {
   using accv = f32x4;
   static constexpr int EPL = 4, KSTEP = 16;
   static constexpr bool ROWS4 = true;
-  __device__ static constexpr int drow(int g, int r) { return 4 * g + r; }
+  __host__ __device__ static constexpr int drow(int g, int r) { return 4 * g + r; }
   __device__ static accv mma(frag a, frag b, accv c) {
     c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], b[0], c, 0, 0, 0);
     c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1], b[1], c, 0, 0, 0);
@@ -98,7 +98,7 @@ struct Prec<double> {
   static constexpr int EPL = 2, KSTEP = 8;
   static constexpr bool ROWS4 = false;
   // the FP64 16x16x4 MFMA returns rows g + 4 r in slot r of lane group g (strided)
-  __device__ static constexpr int drow(int g, int r) { return g + 4 * r; }
+  __host__ __device__ static constexpr int drow(int g, int r) { return g + 4 * r; }
   __device__ static accv mma(frag a, frag b, accv c) {
     c = __builtin_amdgcn_mfma_f64_16x16x4f64(a[0], b[0], c, 0, 0, 0);
     c = __builtin_amdgcn_mfma_f64_16x16x4f64(a[1], b[1], c, 0, 0, 0);

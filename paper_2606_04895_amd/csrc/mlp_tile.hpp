@@ -111,7 +111,7 @@ __device__ __forceinline__ int local_tid() {
 }
 
 template <class P>
-__device__ __forceinline__ int lds_off(int k, int c, int KS) {
+__host__ __device__ __forceinline__ int lds_off(int k, int c, int KS) {
   return (int)frag_offset<P>(c, k, KS);  // B fragments: column = chain, k = neuron
 }
 
@@ -323,10 +323,15 @@ __device__ __forceinline__ void lds_load4(const typename P::T* buf, int rt, int 
 }
 
 // Per-tile activation scratch in D-tile order: [layer][rt][ct][lane][4].
+template <int MT>
+__host__ __device__ __forceinline__ int64_t hsave_index(int layer, int RT, int rt, int ct,
+                                                        int lane) {
+  return ((((int64_t)layer * RT + rt) * MT + ct) * 64 + lane) * 4;
+}
 template <class P, int MT>
 __device__ __forceinline__ typename P::acc* hsave_at(typename P::acc* base, int layer, int RT,
                                                      int rt, int ct, int lane) {
-  return base + ((((int64_t)layer * RT + rt) * MT + ct) * 64 + lane) * 4;
+  return base + hsave_index<MT>(layer, RT, rt, ct, lane);
 }
 
 // Buffers of the tile engine for a given storage mode (the caller sets thf, gth, red, outp,
