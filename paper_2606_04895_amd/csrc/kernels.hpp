@@ -288,10 +288,170 @@ __device__ __forceinline__ void plain_chain(const Target& tg, const TView& X, in
 // Target evaluation for a tile of chains: LPo[c0+c] = log pi(x), GXo = grad_x log pi(x).
 // The inbox / intrain flags of every chain stay in LDS (mi) after the call.
 // ---------------------------------------------------------------------------------------
+// ---------------------------------------------------------------------------------------
+// Lane-group form of the FP64 work around the emulator (d <= kGroupD): chain c of the tile
+// is held by the eight consecutive threads 8c .. 8c + 7, thread 8c + i holding component i,
+// so sums over components are shuffles inside one wave.  One evaluation's FP64 work (its
+// log pi and gradient, the sampler's update and the next proposal's inputs) then runs
+// between the two barriers that the emulator needs anyway, instead of as (component,
+// chain) loops separated by barriers.  Every sum keeps the component order of the loop
+// form.  Shuffles run in control flow that is uniform over a chain's eight threads.
+// ---------------------------------------------------------------------------------------
+constexpr int kGroupD = 8;
+
 template <class P, int MT>
+__device__ __forceinline__ bool group_path(const KArgs& a) {
+  using IP = typename InPrec<P>::type;
+  // The FP32 instantiation keeps the loop form: with the lane-group code, this compiler
+  // (ROCm 7.2) stops on an instruction-selection error in that translation unit.
+  if constexpr (sizeof(typename P::T) == 4) return false;
+  return 8 * 16 * MT <= kThreads && a.tg.d <= kGroupD && a.mp.ks1 * IP::KSTEP <= 2 * kGroupD;
+}
+
+// A chain's eight threads: gb = 4 * (first lane of the group), the byte index of
+// ds_bpermute.
+__device__ __forceinline__ int grp_base(int tid) { return (tid & 56) << 2; }
+
+// v of every component of this thread's chain (eight independent lane permutes, issued
+// together)
+__device__ __forceinline__ void grp_gather(double v, int gb, double (&o)[kGroupD]) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const int lo = (int)(unsigned)b, hi = (int)(unsigned)(b >> 32);
+  unsigned l[kGroupD], h[kGroupD];
+#pragma unroll
+  for (int j = 0; j < kGroupD; ++j) {
+    l[j] = (unsigned)__builtin_amdgcn_ds_bpermute(gb + 4 * j, lo);
+    h[j] = (unsigned)__builtin_amdgcn_ds_bpermute(gb + 4 * j, hi);
+  }
+#pragma unroll
+  for (int j = 0; j < kGroupD; ++j)
+    o[j] = __builtin_bit_cast(double, ((unsigned long long)h[j] << 32) | l[j]);
+}
+
+// v of component j (runtime j) of this thread's chain
+__device__ __forceinline__ double grp_at(double v, int gb, int j) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_ds_bpermute(gb + 4 * j, (int)(unsigned)b);
+  const unsigned hi = (unsigned)__builtin_amdgcn_ds_bpermute(gb + 4 * j, (int)(unsigned)(b >> 32));
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+__device__ __forceinline__ int grp_and(int b) {
+  b &= __shfl_xor(b, 1, 64);
+  b &= __shfl_xor(b, 2, 64);
+  b &= __shfl_xor(b, 4, 64);
+  return b;
+}
+
+// Loads in the lane-group code are unconditional, at indices clamped into range, and only
+// the arithmetic is masked: a load under a per-lane condition becomes a branch with its own
+// wait, and the eight terms of a sum would then run one memory latency apart.
+__device__ __forceinline__ int clampd(int v, int d) { return v < d ? v : d - 1; }
+
+// component i of mu + L z
+__device__ __forceinline__ double grp_affine(const double* __restrict__ mu,
+                                             const double* __restrict__ Lw, int d, int i, int gb,
+                                             double z) {
+  const int ii = clampd(i, d);
+  double zs[kGroupD], l[kGroupD];
+#pragma unroll
+  for (int j = 0; j < kGroupD; ++j) l[j] = Lw[ii * d + clampd(j, d)];
+  const double m = mu[ii];
+  grp_gather(z, gb, zs);
+  double v = 0;
+#pragma unroll
+  for (int j = 0; j < kGroupD; ++j)
+    if (j <= i && i < d) v += l[j] * zs[j];
+  return i < d ? m + v : 0.0;
+}
+
+// component i of L^T g
+__device__ __forceinline__ double grp_lt(const double* __restrict__ Lw, int d, int i, int gb,
+                                         double g) {
+  const int ii = clampd(i, d);
+  double gs[kGroupD], l[kGroupD];
+#pragma unroll
+  for (int j = 0; j < kGroupD; ++j) l[j] = Lw[clampd(j, d) * d + ii];
+  grp_gather(g, gb, gs);
+  double v = 0;
+#pragma unroll
+  for (int j = 0; j < kGroupD; ++j)
+    if (j >= i && j < d) v += l[j] * gs[j];
+  return v;
+}
+
+// component i of L^{-1}(x - mu) (forward substitution, repeated in each thread of the chain)
+__device__ __forceinline__ double grp_whiten(const double* __restrict__ mu,
+                                             const double* __restrict__ Lw, int d, int i, int gb,
+                                             double x) {
+  double xs[kGroupD], z[kGroupD], zi = 0.0;
+  grp_gather(x, gb, xs);
+#pragma unroll
+  for (int k = 0; k < kGroupD; ++k) {
+    const double xk = xs[k];
+    z[k] = 0.0;
+    if (k < d) {
+      double r = xk - mu[k];
+#pragma unroll
+      for (int j = 0; j < kGroupD; ++j)
+        if (j < k) r -= Lw[k * d + j] * z[j];
+      z[k] = r / Lw[k * d + k];
+    }
+    if (k == i) zi = z[k];
+  }
+  return zi;
+}
+
+// Emulator input of chain c from its proposal x (component i in this thread): t = (x -
+// center) * invscale as B fragments of the input layer (zero for padding chains and
+// components), and the chain's in-box / in-training-box flags.
+template <class P, int MT>
+__device__ __forceinline__ void grp_stage(const KArgs& a, char* smem, int c, int i, bool valid,
+                                          double x) {
+  using IP = typename InPrec<P>::type;
+  constexpr int M = 16 * MT;
+  const Target& tg = a.tg;
+  const int d = tg.d, ks1 = a.mp.ks1, K1 = ks1 * IP::KSTEP;
+  const int ii = clampd(i, d);
+  const double ce = tg.in_center[ii], is = tg.in_invscale[ii], lo = tg.lower[ii],
+               hi = tg.upper[ii];
+  int ib = 1, it = 1;
+  double v = 0.0;
+  if (valid && i < d) {
+    v = (x - ce) * is;
+    ib = (x >= lo) & (x <= hi);
+  }
+  if (tg.plain_mode == 1) {
+    const double tlo = tg.train_lo[ii], thi = tg.train_hi[ii];
+    if (valid && i < d) it = (x >= tlo) & (x <= thi);
+  }
+  // the padded input width K1 is at most 16: thread i also clears slot i + 8
+  typename IP::T* thf = (typename IP::T*)(smem + a.lds.th);
+  if (i < K1) thf[frag_offset<IP>(c, i, ks1)] = (typename IP::T)v;
+  if (i + kGroupD < K1) thf[frag_offset<IP>(c, i + kGroupD, ks1)] = (typename IP::T)0.0;
+  ib = grp_and(ib);
+  it = grp_and(it);
+  if (i == 0) {
+    int* inbox = (int*)(smem + a.lds.mi);
+    inbox[c] = ib;
+    inbox[M + c] = tg.plain_mode == 2 ? 0 : it;
+  }
+}
+
+// No continuation after the evaluation.
+struct NoPost {
+  __device__ __forceinline__ void operator()(int, int, bool, double, double, double) const {}
+};
+
+// Target evaluation for a tile.  staged: the caller wrote the emulator inputs and flags
+// (grp_stage).  On the lane-group path, post(c, i, valid, x_i, g_i, log pi) runs in every
+// thread of the tile's chains after log pi and its gradient are written (x_i and g_i this
+// thread's components of the point and of grad_x log pi, g_i = 0 without grad), before the
+// closing barrier.
+template <class P, int MT, class Post>
 __device__ __forceinline__ void eval_tile(const KArgs& a, char* smem, typename P::acc* hsave,
                                           const TView& X, int mv, double* LPo, const TView& GXo,
-                                          bool grad, bool box) {
+                                          bool grad, bool box, bool staged, const Post& post) {
   using acc = typename P::acc;
   using vec = typename P::vec;
   using IP = typename InPrec<P>::type;
@@ -310,24 +470,26 @@ __device__ __forceinline__ void eval_tile(const KArgs& a, char* smem, typename P
   int* intrain = inbox + M;
 
   // normalised inputs t = (x - center) * invscale; padding chains and components are 0
-  const int K1 = a.mp.ks1 * IP::KSTEP;
-  for (int e = tid; e < M * K1; e += kThreads) {
-    const int c = e / K1, i = e % K1;
-    double v = 0.0;
-    if (i < d && c < mv) v = (X(i, c) - tg.in_center[i]) * tg.in_invscale[i];
-    store_t<P>(s, a.mp, c, i, v);
-  }
-  for (int c = tid; c < M; c += kThreads) {
-    int ib = 1, it = 1;
-    if (c < mv) {
-      for (int i = 0; i < d; ++i) {
-        const double xv = X(i, c);
-        ib &= (xv >= tg.lower[i]) & (xv <= tg.upper[i]);
-        if (tg.plain_mode == 1) it &= (xv >= tg.train_lo[i]) & (xv <= tg.train_hi[i]);
-      }
+  if (!staged) {
+    const int K1 = a.mp.ks1 * IP::KSTEP;
+    for (int e = tid; e < M * K1; e += kThreads) {
+      const int c = e / K1, i = e % K1;
+      double v = 0.0;
+      if (i < d && c < mv) v = (X(i, c) - tg.in_center[i]) * tg.in_invscale[i];
+      store_t<P>(s, a.mp, c, i, v);
     }
-    inbox[c] = ib;
-    intrain[c] = tg.plain_mode == 2 ? 0 : it;
+    for (int c = tid; c < M; c += kThreads) {
+      int ib = 1, it = 1;
+      if (c < mv) {
+        for (int i = 0; i < d; ++i) {
+          const double xv = X(i, c);
+          ib &= (xv >= tg.lower[i]) & (xv <= tg.upper[i]);
+          if (tg.plain_mode == 1) it &= (xv >= tg.train_lo[i]) & (xv <= tg.train_hi[i]);
+        }
+      }
+      inbox[c] = ib;
+      intrain[c] = tg.plain_mode == 2 ? 0 : it;
+    }
   }
 
   // the input layer joins the barrier that publishes the inputs and flags
@@ -348,6 +510,88 @@ __device__ __forceinline__ void eval_tile(const KArgs& a, char* smem, typename P
     for (int c = 0; c < mv; ++c) {
       if (!intrain[c]) plain_chain(tg, X, c, grad, psc, pv + c, pgr + c * d);
     }
+  }
+  if (group_path<P, MT>(a)) {
+    if (tid < 8 * M) {
+      const int c = tid >> 3, i = tid & 7, gb = grp_base(tid);
+      const int ii = clampd(i, d), cc = clampd(c, mv);
+      const bool valid = c < mv, act = valid && i < d;
+      const double xr = X(ii, cc);
+      const double x = act ? xr : 0.0;
+      const bool use_mlp = tg.plain_mode == 0 || (tg.plain_mode == 1 && intrain[c]);
+      const int ib = inbox[c];
+      double lp = tg.offset, PRi = 0.0;
+      if (tg.gauss_coef != 0.0) {
+        double y = x;
+        if (tg.tw_v >= 0) {
+          const double xu = grp_at(x, gb, tg.tw_u);
+          if (i == tg.tw_v) {
+            const double du = xu - tg.tw_center;
+            y = y + tg.tw_beta * (du * du - tg.tw_kappa);
+          }
+        }
+        double pr[kGroupD];
+#pragma unroll
+        for (int j = 0; j < kGroupD; ++j) pr[j] = tg.gprec[ii * d + clampd(j, d)];
+        const double gm = tg.gmean[ii];
+        const double R = act ? y - gm : 0.0;
+        double Rs[kGroupD], Ps[kGroupD];
+        grp_gather(R, gb, Rs);
+        double v = 0;
+#pragma unroll
+        for (int j = 0; j < kGroupD; ++j)
+          if (act && j < d) v += pr[j] * Rs[j];
+        PRi = v;
+        grp_gather(PRi, gb, Ps);
+        double q = 0;
+#pragma unroll
+        for (int j = 0; j < kGroupD; ++j)
+          if (j < d) q += Rs[j] * Ps[j];
+        lp += tg.gauss_coef * (-0.5 * q);
+      }
+      lp += use_mlp ? tg.mlp_coef * (double)s.out[c] : pv[c];
+      if (tg.box_penalty) {
+        if (!ib) {
+          double dp, ps[kGroupD];
+          grp_gather(act ? box_pen(tg, i, x, &dp) : 0.0, gb, ps);
+#pragma unroll
+          for (int j = 0; j < kGroupD; ++j)
+            if (j < d) lp -= ps[j];
+        }
+      } else if (box && !ib) {
+        lp = -INFINITY;
+      }
+      if (valid && i == 0) LPo[c] = lp;
+      double g = 0.0;
+      if (grad) {
+        if (tg.gauss_coef != 0.0) {
+          g = -PRi;
+          if (tg.tw_v >= 0) {
+            const double pv_ = grp_at(PRi, gb, tg.tw_v), xu = grp_at(x, gb, tg.tw_u);
+            if (i == tg.tw_u) {
+              const double du = xu - tg.tw_center;
+              g += -pv_ * 2.0 * tg.tw_beta * du;
+            }
+          }
+          g *= tg.gauss_coef;
+        }
+        const double gt = (double)s.gth[c * d + ii], is = tg.in_invscale[ii];
+        if (act) {
+          g += use_mlp ? tg.mlp_coef * gt * is : pgr[c * d + i];
+          if (tg.box_penalty && !ib) {
+            double dp;
+            box_pen(tg, i, x, &dp);
+            g -= dp;
+          }
+          GXo(i, c) = g;
+        } else {
+          g = 0.0;
+        }
+      }
+      post(c, i, valid, x, g, lp);
+    }
+    __syncthreads();
+    return;
   }
   if (tg.gauss_coef != 0.0) {
     for (int e = tid; e < d * M; e += kThreads) {
@@ -415,6 +659,13 @@ __device__ __forceinline__ void eval_tile(const KArgs& a, char* smem, typename P
     }
   }
   __syncthreads();
+}
+
+template <class P, int MT>
+__device__ __forceinline__ void eval_tile(const KArgs& a, char* smem, typename P::acc* hsave,
+                                          const TView& X, int mv, double* LPo, const TView& GXo,
+                                          bool grad, bool box) {
+  eval_tile<P, MT>(a, smem, hsave, X, mv, LPo, GXo, grad, box, false, NoPost{});
 }
 
 // ---------------------------------------------------------------------------------------
@@ -605,6 +856,81 @@ __device__ __forceinline__ void mala_tile(const KArgs& a, char* smem, typename P
   int* flag = inbox + 2 * M;
   const double* mult = a.step_mult;  // per-dimension steps eps_i = eps m_i when set
   const double sq = sqrt(2.0 * eps);
+  if (group_path<P, MT>(a)) {
+    // lane groups (the expressions of the loop form below, in their order): whitening,
+    // drift and noise and the proposal here; reverse drift, acceptance and commit in the
+    // evaluation's continuation.  The chain's tally lives in thread 8c.
+    if (tid < 8 * M) {
+      const int c = tid >> 3, i = tid & 7, gb = grp_base(tid);
+      const int ii = clampd(i, d), cc = clampd(c, mv);
+      const bool valid = c < mv, act = valid && i < d;
+      const double xr = S.x[ii * S.Np + c0 + cc], gr = GX(ii, cc);
+      const double x = act ? xr : 0.0;
+      const double z = grp_whiten(a.wh.mu, Lw, d, i, gb, x);
+      const double gz = grp_lt(Lw, d, i, gb, act ? gr : 0.0);
+      double zp = 0.0;
+      if (act) {
+        const double ei = mult ? eps * mult[i] : eps, sqi = mult ? sqrt(2.0 * ei) : sq;
+        zp = z + ei * gz + sqi * normal_dim(a.rng, c0 + c, t, kStreamNormal, 0, i);
+        T.z(i, c) = z;
+        T.gz(i, c) = gz;
+        T.zp(i, c) = zp;
+      }
+      const double xp = grp_affine(a.wh.mu, Lw, d, i, gb, zp);
+      if (act) T.xp(i, c) = xp;
+      grp_stage<P, MT>(a, smem, c, i, valid, xp);
+    }
+    auto post = [&](int c, int i, bool valid, double x, double g, double lp) {
+      const bool act = valid && i < d;
+      const int gb = grp_base(local_tid()), ii = clampd(i, d), cc = clampd(c, mv);
+      const double zr = T.z(ii, cc), zpr = T.zp(ii, cc), gzr = T.gz(ii, cc);
+      const double gzp = grp_lt(Lw, d, i, gb, g);
+      const double ei = mult ? eps * mult[ii] : eps;
+      double df = 0.0, dr = 0.0;
+      if (act) {
+        df = zpr - zr - ei * gzr;
+        dr = zr - zpr - ei * gzp;
+      }
+      double fwd = 0, rev = 0, dfs[kGroupD], drs[kGroupD];
+      grp_gather(df, gb, dfs);
+      grp_gather(dr, gb, drs);
+      if (mult) {
+        double es[kGroupD];
+        grp_gather(ei, gb, es);
+#pragma unroll
+        for (int j = 0; j < kGroupD; ++j) {
+          if (j < d) {
+            fwd += dfs[j] * dfs[j] / (4.0 * es[j]);
+            rev += drs[j] * drs[j] / (4.0 * es[j]);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < kGroupD; ++j) {
+          if (j < d) {
+            fwd += dfs[j] * dfs[j];
+            rev += drs[j] * drs[j];
+          }
+        }
+        fwd /= 4.0 * eps;
+        rev /= 4.0 * eps;
+      }
+      int acc = 0;
+      if (valid && i == 0) {
+        const int64_t ch = c0 + c;
+        const double la = lp - S.lp[ch] + (-rev) - (-fwd);
+        acc = decide(a, ty, ch, t, 0, la, lp, inbox[c]) ? 1 : 0;
+        if (acc) S.lp[ch] = lp;
+      }
+      acc = __builtin_amdgcn_ds_bpermute(gb, acc);  // chain c's decision, from thread 8c
+      if (acc && act) {
+        S.x[i * S.Np + c0 + c] = x;
+        S.gx[i * S.Np + c0 + c] = g;
+      }
+    };
+    eval_tile<P, MT>(a, smem, hsave, T.xp, mv, T.lpp, T.gxp, true, true, true, post);
+    return;
+  }
   tile_whiten(a.wh.mu, Lw, d, mv, TView{S.x + c0, S.Np}, T.z);
   for (int e = tid; e < d * M; e += kThreads) {
     const int i = e / M, c = e % M;
@@ -670,6 +996,80 @@ __device__ __forceinline__ void hmc_tile(const KArgs& a, char* smem, typename P:
   int* flag = inbox + 2 * M;
   double* h0 = (double*)(smem + a.lds.md);
   const double he = 0.5 * eps;
+  if (group_path<P, MT>(a)) {
+    // lane groups (the expressions of the loop form below, in their order): start, first
+    // half kick and drift and the first proposal here; each evaluation's closing half kick,
+    // the next half kick, drift and proposal, or after the last one accept / reject and
+    // commit, in the evaluation's continuation.  The chain's tally lives in thread 8c.
+    if (tid < 8 * M) {
+      const int c = tid >> 3, i = tid & 7, gb = grp_base(tid);
+      const int ii = clampd(i, d), cc = clampd(c, mv);
+      const bool valid = c < mv, act = valid && i < d;
+      const double xr = S.x[ii * S.Np + c0 + cc], gr = GX(ii, cc);
+      const double x = act ? xr : 0.0;
+      const double z = grp_whiten(a.wh.mu, Lw, d, i, gb, x);
+      const double q = act ? normal_dim(a.rng, c0 + c, t, kStreamNormal, 0, i) : 0.0;
+      double k = 0, qs[kGroupD];
+      grp_gather(q, gb, qs);
+#pragma unroll
+      for (int j = 0; j < kGroupD; ++j)
+        if (j < d) k += qs[j] * qs[j];
+      const double gz = grp_lt(Lw, d, i, gb, act ? gr : 0.0);
+      const double qh = q + he * gz;
+      const double zp = z + eps * qh;
+      const double xp = grp_affine(a.wh.mu, Lw, d, i, gb, zp);
+      if (act) {
+        T.q(i, c) = qh;
+        T.zp(i, c) = zp;
+        T.xp(i, c) = xp;
+      }
+      if (valid && i == 0) h0[c] = -S.lp[c0 + c] + 0.5 * k;
+      grp_stage<P, MT>(a, smem, c, i, valid, xp);
+    }
+    for (int l = 0; l < a.n_leap; ++l) {
+      const bool last = l + 1 == a.n_leap;
+      auto post = [&](int c, int i, bool valid, double x, double g, double lp) {
+        const bool act = valid && i < d;
+        const int gb = grp_base(local_tid()), ii = clampd(i, d), cc = clampd(c, mv);
+        const double qr = T.q(ii, cc), zr = T.zp(ii, cc);
+        const double gz = grp_lt(Lw, d, i, gb, g);
+        const double q = (act ? qr : 0.0) + he * gz;
+        if (!last) {
+          const double qh = q + he * gz;
+          const double zp = (act ? zr : 0.0) + eps * qh;
+          const double xp = grp_affine(a.wh.mu, Lw, d, i, gb, zp);
+          if (act) {
+            T.q(i, c) = qh;
+            T.zp(i, c) = zp;
+            T.xp(i, c) = xp;
+          }
+          grp_stage<P, MT>(a, smem, c, i, valid, xp);
+          return;
+        }
+        double k = 0, qs[kGroupD];
+        grp_gather(q, gb, qs);
+#pragma unroll
+        for (int j = 0; j < kGroupD; ++j)
+          if (j < d) k += qs[j] * qs[j];
+        int acc = 0;
+        if (valid && i == 0) {
+          const int64_t ch = c0 + c;
+          const double lp1 = (inbox[c] || a.tg.box_penalty) ? lp : -INFINITY;
+          const double h1 = -lp1 + 0.5 * k;
+          const double la = h0[c] - h1;
+          acc = decide(a, ty, ch, t, 0, la, lp1, inbox[c]) ? 1 : 0;
+          if (acc) S.lp[ch] = lp1;
+        }
+        acc = __builtin_amdgcn_ds_bpermute(gb, acc);  // chain c's decision, from thread 8c
+        if (acc && act) {
+          S.x[i * S.Np + c0 + c] = x;
+          S.gx[i * S.Np + c0 + c] = g;
+        }
+      };
+      eval_tile<P, MT>(a, smem, hsave, T.xp, mv, T.lpp, T.gxp, true, false, true, post);
+    }
+    return;
+  }
   tile_whiten(a.wh.mu, Lw, d, mv, TView{S.x + c0, S.Np}, T.z);
   // momentum, copies of the start point, whitened start gradient
   for (int e = tid; e < d * M; e += kThreads) {
@@ -1133,7 +1533,10 @@ __global__ __launch_bounds__(kThreads, 1) void step_kernel(KArgs a) {
       if constexpr (!kHalves) record_tile(a, s, a.tg.d, M, mv, c0);
     }
     if constexpr (SAMPLER != 4) {
-      if (a.n_steps > 0 && local_tid() < mv) flush_tally(a.st, c0 + local_tid(), ty);
+      // the lane-group MALA / HMC keep chain c's tally in thread 8c, the others in thread c
+      const int own = ((SAMPLER == 1 || SAMPLER == 2) && group_path<P, MT>(a)) ? 8 : 1;
+      const int tid = local_tid();
+      if (a.n_steps > 0 && tid % own == 0 && tid / own < mv) flush_tally(a.st, c0 + tid / own, ty);
     }
   }
 }
