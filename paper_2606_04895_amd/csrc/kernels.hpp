@@ -302,9 +302,6 @@ constexpr int kGroupD = 8;
 template <class P, int MT>
 __device__ __forceinline__ bool group_path(const KArgs& a) {
   using IP = typename InPrec<P>::type;
-  // The FP32 instantiation keeps the loop form: with the lane-group code, this compiler
-  // (ROCm 7.2) stops on an instruction-selection error in that translation unit.
-  if constexpr (sizeof(typename P::T) == 4) return false;
   return 8 * 16 * MT <= kThreads && a.tg.d <= kGroupD && a.mp.ks1 * IP::KSTEP <= 2 * kGroupD;
 }
 
