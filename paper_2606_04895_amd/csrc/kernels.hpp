@@ -78,6 +78,17 @@ struct LdsLayout {
 
 __host__ __device__ inline int align16(int v) { return (v + 15) & ~15; }
 
+// The tile scratch and the staged constants live in LDS or in global memory depending on
+// the layout, and are reached through generic pointers either way.  Pointers into LDS that
+// stand in for global arrays pass through here, so that the optimiser treats them as
+// plain generic pointers: with their LDS origin visible, this compiler (ROCm 7.2) can emit
+// an invalid aperture comparison for them.
+template <class T>
+__device__ __forceinline__ T* generic_ptr(T* p) {
+  asm volatile("" : "+s"(p));
+  return p;
+}
+
 // Union region: {activation slots or ping-pong buffers + delta buffers} during the MLP,
 // {R, PR, plain results, plain scratch} during the FP64 assembly.
 // The input buffer holds M x k1 values of isize bytes (d padded to the input layer's
@@ -189,6 +200,31 @@ __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
+}
+
+// acc + SIGN * sum_{j0 <= j < j1} a(j) b(j), accumulated in ascending j.  The loads of
+// eight consecutive terms are issued together (indices clamped into [j0, j1), the clamped
+// copies' products masked out), so a long sum waits one memory latency per eight terms
+// rather than one per term.
+template <int SIGN, class FA, class FB>
+__device__ __forceinline__ double dot8(double acc, int j0, int j1, const FA& fa, const FB& fb) {
+  for (int jb = j0; jb < j1; jb += 8) {
+    double x[8], y[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int j = jb + u < j1 ? jb + u : j1 - 1;
+      x[u] = fa(j);
+      y[u] = fb(j);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (jb + u < j1) {
+        if constexpr (SIGN > 0) acc += x[u] * y[u];
+        else acc -= x[u] * y[u];
+      }
+    }
+  }
+  return acc;
 }
 
 __device__ __forceinline__ void plain_chain(const Target& tg, const TView& X, int c, bool grad,
@@ -478,10 +514,24 @@ __device__ __forceinline__ void eval_tile(const KArgs& a, char* smem, typename P
     for (int c = tid; c < M; c += kThreads) {
       int ib = 1, it = 1;
       if (c < mv) {
-        for (int i = 0; i < d; ++i) {
-          const double xv = X(i, c);
-          ib &= (xv >= tg.lower[i]) & (xv <= tg.upper[i]);
-          if (tg.plain_mode == 1) it &= (xv >= tg.train_lo[i]) & (xv <= tg.train_hi[i]);
+        // in blocks of eight components, loads first (see dot8)
+        for (int i0 = 0; i0 < d; i0 += 8) {
+          double xv[8], lo[8], hi[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int i = i0 + u < d ? i0 + u : d - 1;
+            xv[u] = X(i, c);
+            lo[u] = tg.lower[i];
+            hi[u] = tg.upper[i];
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            if (i0 + u < d) {
+              ib &= (xv[u] >= lo[u]) & (xv[u] <= hi[u]);
+              if (tg.plain_mode == 1)
+                it &= (xv[u] >= tg.train_lo[i0 + u]) & (xv[u] <= tg.train_hi[i0 + u]);
+            }
+          }
         }
       }
       inbox[c] = ib;
@@ -606,9 +656,8 @@ __device__ __forceinline__ void eval_tile(const KArgs& a, char* smem, typename P
     __syncthreads();
     for (int e = tid; e < d * M; e += kThreads) {
       const int i = e / M, c = e % M;
-      double v = 0;
-      for (int j = 0; j < d; ++j) v += tg.gprec[i * d + j] * R[j * M + c];
-      PR[e] = v;
+      PR[e] = dot8<1>(0.0, 0, d, [&](int j) { return tg.gprec[i * d + j]; },
+                      [&](int j) { return R[j * M + c]; });
     }
     __syncthreads();
   }
@@ -616,8 +665,8 @@ __device__ __forceinline__ void eval_tile(const KArgs& a, char* smem, typename P
     const int c = tid;
     double lp = tg.offset;
     if (tg.gauss_coef != 0.0) {
-      double q = 0;
-      for (int i = 0; i < d; ++i) q += R[i * M + c] * PR[i * M + c];
+      const double q = dot8<1>(0.0, 0, d, [&](int i) { return R[i * M + c]; },
+                               [&](int i) { return PR[i * M + c]; });
       lp += tg.gauss_coef * (-0.5 * q);
     }
     const bool use_mlp = tg.plain_mode == 0 || (tg.plain_mode == 1 && intrain[c]);
@@ -680,7 +729,7 @@ __device__ __forceinline__ Scratch tile_scratch(const KArgs& a, char* smem, int6
   constexpr int M = 16 * MT;
   Scratch T;
   if (a.lds.st >= 0) {
-    double* b = (double*)(smem + a.lds.st);
+    double* b = generic_ptr((double*)(smem + a.lds.st));
     const int64_t n = (int64_t)a.tg.d * M;
     T.z = TView{b, M};
     T.zp = TView{b + n, M};
@@ -713,8 +762,8 @@ __device__ __forceinline__ void tile_affine(const double* __restrict__ mu,
   for (int e = local_tid(); e < d * M; e += kThreads) {
     const int i = e / M, c = e % M;
     if (c >= mv) continue;
-    double v = 0;
-    for (int j = 0; j <= i; ++j) v += Lw[i * d + j] * Z(j, c);
+    const double v = dot8<1>(0.0, 0, i + 1, [&](int j) { return Lw[i * d + j]; },
+                             [&](int j) { return Z(j, c); });
     Xo(i, c) = mu[i] + v;
   }
 }
@@ -729,8 +778,8 @@ __device__ __forceinline__ void tile_whiten(const double* __restrict__ mu,
   const int c = local_tid();
   if (c < mv) {
     for (int i = 0; i < d; ++i) {
-      double r = X(i, c) - mu[i];
-      for (int j = 0; j < i; ++j) r -= Lw[i * d + j] * Z(j, c);
+      const double r = dot8<-1>(X(i, c) - mu[i], 0, i, [&](int j) { return Lw[i * d + j]; },
+                                [&](int j) { return Z(j, c); });
       Z(i, c) = r / Lw[i * d + i];
     }
   }
@@ -740,9 +789,7 @@ __device__ __forceinline__ void tile_whiten(const double* __restrict__ mu,
 // (L^T g)_i = sum_{j >= i} L[j][i] g_j for chain c
 __device__ __forceinline__ double lt_dot(const double* __restrict__ Lw, int d, int i,
                                          const TView& G, int c) {
-  double v = 0;
-  for (int j = i; j < d; ++j) v += Lw[j * d + i] * G(j, c);
-  return v;
+  return dot8<1>(0.0, i, d, [&](int j) { return Lw[j * d + i]; }, [&](int j) { return G(j, c); });
 }
 
 __device__ __forceinline__ double accept_prob(double la) {
@@ -950,22 +997,37 @@ __device__ __forceinline__ void mala_tile(const KArgs& a, char* smem, typename P
   if (tid < mv) {
     const int c = tid;
     const int64_t ch = c0 + c;
+    // sums over the components in blocks of eight, loads first (see dot8); with mult the
+    // per-dimension terms |.|^2 / (4 eps_i)
     double fwd = 0, rev = 0;
-    if (mult) {  // sums of the per-dimension terms |.|^2 / (4 eps_i)
-      for (int i = 0; i < d; ++i) {
-        const double ei = eps * mult[i];
-        const double df = T.zp(i, c) - T.z(i, c) - ei * T.gz(i, c);
-        const double dr = T.z(i, c) - T.zp(i, c) - ei * T.gzp(i, c);
-        fwd += df * df / (4.0 * ei);
-        rev += dr * dr / (4.0 * ei);
+    for (int i0 = 0; i0 < d; i0 += 8) {
+      double zp[8], z[8], gz[8], gzp[8], ml[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int i = i0 + u < d ? i0 + u : d - 1;
+        zp[u] = T.zp(i, c);
+        z[u] = T.z(i, c);
+        gz[u] = T.gz(i, c);
+        gzp[u] = T.gzp(i, c);
+        ml[u] = mult ? mult[i] : 1.0;
       }
-    } else {
-      for (int i = 0; i < d; ++i) {
-        const double df = T.zp(i, c) - T.z(i, c) - eps * T.gz(i, c);
-        const double dr = T.z(i, c) - T.zp(i, c) - eps * T.gzp(i, c);
-        fwd += df * df;
-        rev += dr * dr;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (i0 + u < d) {
+          const double ei = mult ? eps * ml[u] : eps;
+          const double df = zp[u] - z[u] - ei * gz[u];
+          const double dr = z[u] - zp[u] - ei * gzp[u];
+          if (mult) {
+            fwd += df * df / (4.0 * ei);
+            rev += dr * dr / (4.0 * ei);
+          } else {
+            fwd += df * df;
+            rev += dr * dr;
+          }
+        }
       }
+    }
+    if (!mult) {
       fwd /= 4.0 * eps;
       rev /= 4.0 * eps;
     }
@@ -1079,7 +1141,7 @@ __device__ __forceinline__ void hmc_tile(const KArgs& a, char* smem, typename P:
   __syncthreads();
   if (tid < mv) {
     double k = 0;
-    for (int i = 0; i < d; ++i) k += T.q(i, tid) * T.q(i, tid);
+    k = dot8<1>(k, 0, d, [&](int i) { return T.q(i, tid); }, [&](int i) { return T.q(i, tid); });
     h0[tid] = -S.lp[c0 + tid] + 0.5 * k;
   }
   __syncthreads();
@@ -1107,7 +1169,7 @@ __device__ __forceinline__ void hmc_tile(const KArgs& a, char* smem, typename P:
   if (tid < mv) {
     const int64_t ch = c0 + tid;
     double k = 0;
-    for (int i = 0; i < d; ++i) k += T.q(i, tid) * T.q(i, tid);
+    k = dot8<1>(k, 0, d, [&](int i) { return T.q(i, tid); }, [&](int i) { return T.q(i, tid); });
     const double lp1 = (inbox[tid] || a.tg.box_penalty) ? T.lpp[tid] : -INFINITY;
     const double h1 = -lp1 + 0.5 * k;
     const double la = h0[tid] - h1;
@@ -1462,7 +1524,7 @@ __device__ __forceinline__ void stage_constants(KArgs& a, char* smem) {
     const int nf = a.lds.w1f_bytes / 16, nt = a.lds.w1t_bytes / 16;
     const i4* __restrict__ sf = (const i4*)a.mp.w1f;
     const i4* __restrict__ st = (const i4*)a.mp.w1t;
-    i4* df = (i4*)(smem + a.lds.w1);
+    i4* df = generic_ptr((i4*)(smem + a.lds.w1));
     i4* dt = df + nf;
     for (int e = local_tid(); e < nf; e += kThreads) df[e] = sf[e];
     for (int e = local_tid(); e < nt; e += kThreads) dt[e] = st[e];
@@ -1472,7 +1534,7 @@ __device__ __forceinline__ void stage_constants(KArgs& a, char* smem) {
   }
   if (a.lds.cst < 0) return;
   const int d = a.tg.d, dd = d * d, tid = local_tid();
-  double* c = (double*)(smem + a.lds.cst);
+  double* c = generic_ptr((double*)(smem + a.lds.cst));
   auto copy = [&](const double* src, double* dst, int n) {
     for (int e = tid; e < n; e += kThreads) dst[e] = src[e];
   };
