@@ -194,6 +194,21 @@ def test_lockstep_small(prec, sampler, kw):
     _lockstep(prob, prec, sampler, 262, steps=3, band=band, state_tol=tol, **kw)
 
 
+@pytest.mark.parametrize("d", [8, 9, 12])
+@pytest.mark.parametrize("prec,sampler,kw", [
+    ("fp32", "mala", dict(eps=0.008)),
+    ("fp32", "hmc", dict(eps=0.07, n_leapfrog=5)),
+    ("fp64", "mh", dict(mh_scale=0.5)),
+])
+def test_lockstep_both_forms_of_the_fp64_work(d, prec, sampler, kw):
+    """The FP64 work around the emulator has two forms: eight threads per chain for
+    d <= 8, (component, chain) loops above.  d = 8 is the largest for the first, 9 and 12
+    take the second; twisted pair and a ragged last tile (262 chains) in each."""
+    prob = small_problem(d=d, width=128, n_hidden=3, twist=True)
+    band, tol = (1e-9, 1e-10) if prec == "fp64" else (1e-6, 1e-4)
+    _lockstep(prob, prec, sampler, 262, steps=3, band=band, state_tol=tol, **kw)
+
+
 @pytest.mark.parametrize("sampler,kw", [("mala", dict(eps=0.5)),
                                         ("hmc", dict(eps=0.3, n_leapfrog=10))])
 def test_lockstep_c2_fp32(sampler, kw):

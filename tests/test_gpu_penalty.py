@@ -12,20 +12,22 @@ from workloads import small_problem
 pytestmark = pytest.mark.gpu
 
 
-def _prob():
-    prob = small_problem(d=5, width=128, n_hidden=3, seed=19)
+def _prob(d=5):
+    prob = small_problem(d=d, width=128, n_hidden=3, seed=19)
     # a box of +-2 sigma so that trajectories reach its faces
     sd = np.sqrt(np.diag(prob["closed_cov"]))
     return dict(prob, lower=prob["gauss_mean"] - 2 * sd, upper=prob["gauss_mean"] + 2 * sd,
                 box_penalty=1, penalty_width=0.05)
 
 
+# d = 5 takes the eight-threads-per-chain form of the FP64 work, d = 12 the loop form
+@pytest.mark.parametrize("d", [5, 12])
 @pytest.mark.parametrize("prec,tl,tg", [("fp32", 2e-5, 2e-4), ("fp64", 1e-9, 1e-8)])
-def test_penalised_logL_grad_inside_and_outside(prec, tl, tg):
-    prob = _prob()
+def test_penalised_logL_grad_inside_and_outside(prec, tl, tg, d):
+    prob = _prob(d)
     rng = np.random.default_rng(3)
     width = prob["upper"] - prob["lower"]
-    x = prob["lower"] + rng.uniform(-0.15, 1.15, size=(97, 5)) * width
+    x = prob["lower"] + rng.uniform(-0.15, 1.15, size=(97, d)) * width
     ctx = B.best_init(prob, n_chains=16, precision=prec, seed=1)
     lp, g = B.best_logL_grad(ctx, x.T.copy())
     lo, go = OT.log_target(prob, x)
@@ -44,8 +46,9 @@ def _start_at_face(prob, n, seed):
     return ctx
 
 
-def test_hmc_lockstep_across_the_faces():
-    prob = _prob()
+@pytest.mark.parametrize("d", [5, 12])
+def test_hmc_lockstep_across_the_faces(d):
+    prob = _prob(d)
     seed = 0xBE71
     ctx = _start_at_face(prob, 40, seed)
     crossed = 0
