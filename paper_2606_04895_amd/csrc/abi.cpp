@@ -384,9 +384,12 @@ static int choose_mt(best_ctx* h, const best_config* c) {
   h->MT = mt;
   h->mt_fixed = c->chains_per_block != 0;
   h->lds_h = fits(mt, 1) ? 1 : 0;
-  // the sampler's per-step FP64 scratch goes to LDS too when there is room, and then the
-  // input layer's weights (W_1, W_1^T), which every evaluation reads
-  h->st_lds = layout_for(h->prec, mt, h->H, h->d, h->nh, h->lds_h, 1).total <= kLdsMax ? 1 : 0;
+  // the sampler's per-step FP64 scratch and the launch constants go to LDS too when there is
+  // room (1), else the constants alone when they fit (2), and then the input layer's
+  // weights (W_1, W_1^T), which every evaluation reads
+  h->st_lds = layout_for(h->prec, mt, h->H, h->d, h->nh, h->lds_h, 1).total <= kLdsMax   ? 1
+              : layout_for(h->prec, mt, h->H, h->d, h->nh, h->lds_h, 2).total <= kLdsMax ? 2
+                                                                                         : 0;
   // (never at the cost of a second workgroup per CU)
   const int base = layout_for(h->prec, mt, h->H, h->d, h->nh, h->lds_h, h->st_lds).total;
   const int with = layout_for(h->prec, mt, h->H, h->d, h->nh, h->lds_h, h->st_lds, 1).total;

@@ -93,9 +93,10 @@ __device__ __forceinline__ T* generic_ptr(T* p) {
 // {R, PR, plain results, plain scratch} during the FP64 assembly.
 // The input buffer holds M x k1 values of isize bytes (d padded to the input layer's
 // k-step); waves is the tile workgroup's wave count (per-wave partial sums).
-// With st_lds the per-step FP64 scratch of the tile (7 [d][M] arrays and log pi of the
-// proposals) and the launch's small constant arrays also live in LDS (st, cst >= 0), else
-// they stay in global memory (-1).  With w1_bytes = (w1f, w1t) sizes > 0 the input layer's
+// With st_lds = 1 the per-step FP64 scratch of the tile (7 [d][M] arrays and log pi of the
+// proposals) and the launch's small constant arrays also live in LDS (st, cst >= 0); with
+// st_lds = 2 only the constants do (cst >= 0, st = -1); the others stay in global memory
+// (-1).  With w1_bytes = (w1f, w1t) sizes > 0 the input layer's
 // packed weights W_1 and W_1^T are copied into LDS once per launch (w1 >= 0).
 __host__ __device__ inline LdsLayout lds_layout(int M, int H, int d, int nh, int lds_h,
                                                int tsize, int vsize, int asize, int k1,
@@ -132,9 +133,11 @@ __host__ __device__ inline LdsLayout lds_layout(int M, int H, int d, int nh, int
   L.md = o;  // doubles: 8 per chain
   o = align16(o + 8 * M * 8);
   L.st = L.cst = -1;
-  if (st_lds) {
+  if (st_lds == 1) {
     L.st = o;
     o = align16(o + (7 * d * M + M) * 8);
+  }
+  if (st_lds) {
     L.cst = o;  // launch constants: L, S^-1 (d x d), mu, gauss mean, box, input scaling
     o = align16(o + (2 * d * d + 8 * d) * 8);
   }
@@ -473,8 +476,410 @@ __device__ __forceinline__ void grp_stage(const KArgs& a, char* smem, int c, int
 
 // No continuation after the evaluation.
 struct NoPost {
-  __device__ __forceinline__ void operator()(int, int, bool, double, double, double) const {}
+  template <class... A>
+  __device__ __forceinline__ void operator()(const A&...) const {}
 };
+
+// A continuation written for the wide lane groups (arrays of a thread's two components);
+// eval_tile compiles its wide branch only for these and for NoPost.
+template <class L>
+struct WidePost {
+  L f;
+  template <class... A>
+  __device__ __forceinline__ void operator()(const A&... x) const {
+    f(x...);
+  }
+};
+template <class T>
+struct IsWidePost {
+  static constexpr bool value = false;
+};
+template <class L>
+struct IsWidePost<WidePost<L>> {
+  static constexpr bool value = true;
+};
+template <>
+struct IsWidePost<NoPost> {
+  static constexpr bool value = true;
+};
+
+// ---------------------------------------------------------------------------------------
+// Wide lane groups for 8 < d <= 32 on 32-chain tiles (the width of the 1024-wide networks):
+// sixteen threads per chain, thread 16c + i holding components i and i + 16, sums over the
+// components as blocked in-wave permutes in the component order of the loop form.  Only
+// the 32-chain kernels compile this form: its registers would make the 16-chain kernels
+// spill.
+// ---------------------------------------------------------------------------------------
+constexpr int kGroupW = 32;  // largest d on the wide lane-group path
+
+template <int MT>
+constexpr bool kWide = MT == 2;
+
+template <class P, int MT>
+__device__ __forceinline__ bool wide_path(const KArgs& a) {
+  using IP = typename InPrec<P>::type;
+  const int d = a.tg.d, K1 = a.mp.ks1 * IP::KSTEP;
+  return kWide<MT> && d > kGroupD && d <= kGroupW && K1 <= kGroupW && 16 * 16 * MT <= kThreads;
+}
+
+// gb = 4 * (first lane of this thread's chain), the byte index of ds_bpermute
+template <int G>
+__device__ __forceinline__ int gw_base(int tid) {
+  return (tid & (64 - G)) << 2;
+}
+
+// every component of this thread's chain: o[j + G u] = v[u] of the chain's thread j (eight
+// or sixteen independent lane permutes per value, issued together)
+template <int G, int V>
+__device__ __forceinline__ void gw_gather(const double (&v)[V], int gb, double (&o)[G * V]) {
+  unsigned l[G * V], h[G * V];
+#pragma unroll
+  for (int u = 0; u < V; ++u) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v[u]);
+    const int lo = (int)(unsigned)b, hi = (int)(unsigned)(b >> 32);
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+      l[j + G * u] = (unsigned)__builtin_amdgcn_ds_bpermute(gb + 4 * j, lo);
+      h[j + G * u] = (unsigned)__builtin_amdgcn_ds_bpermute(gb + 4 * j, hi);
+    }
+  }
+#pragma unroll
+  for (int n = 0; n < G * V; ++n)
+    o[n] = __builtin_bit_cast(double, ((unsigned long long)h[n] << 32) | l[n]);
+}
+
+// component j of the chain (j the same in all of its threads)
+template <int G, int V>
+__device__ __forceinline__ double gw_at(const double (&v)[V], int gb, int j) {
+  double src = v[0];
+#pragma unroll
+  for (int u = 1; u < V; ++u)
+    if (j >= G * u) src = v[u];
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, src);
+  const int idx = gb + 4 * (j % G);
+  const unsigned lo = (unsigned)__builtin_amdgcn_ds_bpermute(idx, (int)(unsigned)b);
+  const unsigned hi = (unsigned)__builtin_amdgcn_ds_bpermute(idx, (int)(unsigned)(b >> 32));
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// components jb .. jb + 7 of this thread's chain (jb a multiple of 8, the same in all of the
+// chain's threads)
+template <int G, int V>
+__device__ __forceinline__ void gw_block(const double (&v)[V], int gb, int jb, double (&o)[8]) {
+  double src = v[0];
+#pragma unroll
+  for (int u = 1; u < V; ++u)
+    if (jb >= G * u) src = v[u];
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, src);
+  const int lo = (int)(unsigned)b, hi = (int)(unsigned)(b >> 32), base = gb + 4 * (jb % G);
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const unsigned l = (unsigned)__builtin_amdgcn_ds_bpermute(base + 4 * u, lo);
+    const unsigned h = (unsigned)__builtin_amdgcn_ds_bpermute(base + 4 * u, hi);
+    o[u] = __builtin_bit_cast(double, ((unsigned long long)h << 32) | l);
+  }
+}
+
+// acc + SIGN * sum_{j0 <= j < j1} coef(j) w_j, w_j component j of this chain's v; ascending
+// j, eight components (permutes and coefficient loads) at a time.  j0 and j1 may differ
+// between the chain's threads; the blocks run up to d in all of them (the permutes read
+// the other threads' registers).
+template <int SIGN, int G, int V, class F>
+__device__ __forceinline__ double gw_dotc(double acc, int j0, int j1, int d, const F& coef,
+                                           const double (&v)[V], int gb) {
+#pragma unroll
+  for (int jb = 0; jb < G * V; jb += 8) {
+    if (jb >= d) break;
+    double w[8], cf[8];
+    gw_block<G, V>(v, gb, jb, w);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) cf[u] = coef(jb + u);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (jb + u >= j0 && jb + u < j1) {
+        if constexpr (SIGN > 0) acc += cf[u] * w[u];
+        else acc -= cf[u] * w[u];
+      }
+    }
+  }
+  return acc;
+}
+
+// acc + sum_{j < d} x_j^2 over this chain's components, ascending j
+template <int G, int V>
+__device__ __forceinline__ double gw_sumsq(double acc, int d, const double (&x)[V], int gb) {
+#pragma unroll
+  for (int jb = 0; jb < G * V; jb += 8) {
+    if (jb >= d) break;
+    double w[8];
+    gw_block<G, V>(x, gb, jb, w);
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (jb + u < d) acc += w[u] * w[u];
+  }
+  return acc;
+}
+
+// acc + sum_{j < d} x_j y_j over this chain's components, ascending j
+template <int G, int V>
+__device__ __forceinline__ double gw_dotv(double acc, int d, const double (&x)[V],
+                                           const double (&y)[V], int gb) {
+#pragma unroll
+  for (int jb = 0; jb < G * V; jb += 8) {
+    if (jb >= d) break;
+    double wx[8], wy[8];
+    gw_block<G, V>(x, gb, jb, wx);
+    gw_block<G, V>(y, gb, jb, wy);
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (jb + u < d) acc += wx[u] * wy[u];
+  }
+  return acc;
+}
+
+template <int G>
+__device__ __forceinline__ int gw_and(int b) {
+#pragma unroll
+  for (int o = 1; o < G; o <<= 1) b &= __shfl_xor(b, o, 64);
+  return b;
+}
+
+
+// this thread's components of mu + L z
+template <int G, int V>
+__device__ __forceinline__ void gw_affine(const double* __restrict__ mu,
+                                           const double* __restrict__ Lw, int d, int i, int gb,
+                                           const double (&z)[V], double (&x)[V]) {
+#pragma unroll
+  for (int u = 0; u < V; ++u) {
+    const int k = i + G * u, kk = clampd(k, d);
+    const double m = mu[kk];
+    const double v = gw_dotc<1, G, V>(0.0, 0, k < d ? k + 1 : 0, d,
+                                       [&](int j) { return Lw[kk * d + clampd(j, d)]; }, z, gb);
+    x[u] = k < d ? m + v : 0.0;
+  }
+}
+
+// this thread's components of L^T g
+template <int G, int V>
+__device__ __forceinline__ void gw_lt(const double* __restrict__ Lw, int d, int i, int gb,
+                                       const double (&g)[V], double (&o)[V]) {
+#pragma unroll
+  for (int u = 0; u < V; ++u) {
+    const int k = i + G * u, kk = clampd(k, d);
+    o[u] = gw_dotc<1, G, V>(0.0, k, d, d, [&](int j) { return Lw[clampd(j, d) * d + kk]; }, g,
+                             gb);
+  }
+}
+
+// this thread's components of L^{-1}(x - mu), by forward substitution in the component order
+// of the loop form: with one component per thread every thread repeats the whole
+// substitution; with two, component k is final once the terms of components < k are
+// removed, its thread divides, and every thread of the chain removes its term
+template <int G, int V>
+__device__ __forceinline__ void gw_whiten(const double* __restrict__ mu,
+                                           const double* __restrict__ Lw, int d, int i, int gb,
+                                           const double (&x)[V], double (&zo)[V]) {
+  if constexpr (V == 1) {
+    double xs[G], z[G], zi = 0.0;
+    gw_gather<G, 1>(x, gb, xs);
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      z[k] = 0.0;
+      if (k < d) {
+        double r = xs[k] - mu[k];
+#pragma unroll
+        for (int j = 0; j < G; ++j)
+          if (j < k) r -= Lw[k * d + j] * z[j];
+        z[k] = r / Lw[k * d + k];
+      }
+      if (k == i) zi = z[k];
+    }
+    zo[0] = zi;
+  } else {
+    double r[V];
+    int kk[V];
+#pragma unroll
+    for (int u = 0; u < V; ++u) {
+      kk[u] = clampd(i + G * u, d);
+      r[u] = x[u] - mu[kk[u]];
+      zo[u] = 0.0;
+    }
+    for (int k = 0; k < d; ++k) {
+      const int ku = k / G, kl = k % G;
+      double lk[V];
+#pragma unroll
+      for (int u = 0; u < V; ++u) lk[u] = Lw[kk[u] * d + k];
+      const double dk = Lw[k * d + k];
+#pragma unroll
+      for (int u = 0; u < V; ++u)
+        if (u == ku && i == kl) zo[u] = r[u] / dk;
+      const double zk = gw_at<G, V>(zo, gb, k);
+#pragma unroll
+      for (int u = 0; u < V; ++u)
+        if (i + G * u > k && i + G * u < d) r[u] -= lk[u] * zk;
+    }
+  }
+}
+
+// Emulator input of chain c from its proposal x (this thread's components): t = (x -
+// center) * invscale as B fragments of the input layer (zero for padding chains and
+// components), and the chain's in-box / in-training-box flags.  The padded input width is
+// at most 2 G, so this thread writes slots i and i + G.
+template <class P, int MT, int G, int V>
+__device__ __forceinline__ void gw_stage(const KArgs& a, char* smem, int c, int i, bool valid,
+                                          const double (&x)[V]) {
+  using IP = typename InPrec<P>::type;
+  constexpr int M = 16 * MT;
+  const Target& tg = a.tg;
+  const int d = tg.d, ks1 = a.mp.ks1, K1 = ks1 * IP::KSTEP;
+  typename IP::T* thf = (typename IP::T*)(smem + a.lds.th);
+  int ib = 1, it = 1;
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int k = i + G * u, kk = clampd(k, d);
+    const double ce = tg.in_center[kk], is = tg.in_invscale[kk], lo = tg.lower[kk],
+                 hi = tg.upper[kk];
+    const double xu = u < V ? x[u < V ? u : 0] : 0.0;
+    const bool act = u < V && valid && k < d;
+    double v = 0.0;
+    if (act) {
+      v = (xu - ce) * is;
+      ib &= (xu >= lo) & (xu <= hi);
+    }
+    if (tg.plain_mode == 1) {
+      const double tlo = tg.train_lo[kk], thi = tg.train_hi[kk];
+      if (act) it &= (xu >= tlo) & (xu <= thi);
+    }
+    if (k < K1) thf[frag_offset<IP>(c, k, ks1)] = (typename IP::T)v;
+  }
+  ib = gw_and<G>(ib);
+  it = gw_and<G>(it);
+  if (i == 0) {
+    int* inbox = (int*)(smem + a.lds.mi);
+    inbox[c] = ib;
+    inbox[M + c] = tg.plain_mode == 2 ? 0 : it;
+  }
+}
+
+// Wide lane-group form of the target evaluation (see eval_tile): log pi and its gradient of the
+// tile's chains from X, then post(c, i, valid, x, g, log pi) in every thread of the chains
+// (x and g this thread's components of the point and of grad_x log pi, g = 0 without grad).
+template <class P, int MT, int G, int V, class Post>
+__device__ __forceinline__ void gw_eval(const KArgs& a, const MlpSmem<P>& s, const TView& X,
+                                         int mv, double* LPo, const TView& GXo, bool grad,
+                                         bool box, const double* pv, const double* pgr,
+                                         const int* inbox, const int* intrain,
+                                         const Post& post) {
+  constexpr int M = 16 * MT, N = G * V;
+  const Target& tg = a.tg;
+  const int tid = local_tid(), d = tg.d;
+  if (tid >= G * M) return;
+  const int c = tid / G, i = tid % G, gb = gw_base<G>(tid), cc = clampd(c, mv);
+  const bool valid = c < mv;
+  double x[V];
+  int kk[V];
+  bool act[V];
+#pragma unroll
+  for (int u = 0; u < V; ++u) {
+    kk[u] = clampd(i + G * u, d);
+    act[u] = valid && i + G * u < d;
+    const double xr = X(kk[u], cc);
+    x[u] = act[u] ? xr : 0.0;
+  }
+  const bool use_mlp = tg.plain_mode == 0 || (tg.plain_mode == 1 && intrain[c]);
+  const int ib = inbox[c];
+  double lp = tg.offset, PRv[V];
+#pragma unroll
+  for (int u = 0; u < V; ++u) PRv[u] = 0.0;
+  if (tg.gauss_coef != 0.0) {
+    double R[V];
+    const double xu = tg.tw_v >= 0 ? gw_at<G, V>(x, gb, tg.tw_u) : 0.0;
+#pragma unroll
+    for (int u = 0; u < V; ++u) {
+      double y = x[u];
+      if (tg.tw_v >= 0 && i + G * u == tg.tw_v) {
+        const double du = xu - tg.tw_center;
+        y = y + tg.tw_beta * (du * du - tg.tw_kappa);
+      }
+      const double gm = tg.gmean[kk[u]];
+      R[u] = act[u] ? y - gm : 0.0;
+    }
+    double q = 0;
+    if constexpr (V == 1) {
+      // one component per thread: R and P R gathered once each
+      double Rs[G], Ps[G], pr[G];
+#pragma unroll
+      for (int j = 0; j < G; ++j) pr[j] = tg.gprec[kk[0] * d + clampd(j, d)];
+      gw_gather<G, 1>(R, gb, Rs);
+      double v = 0;
+#pragma unroll
+      for (int j = 0; j < G; ++j)
+        if (act[0] && j < d) v += pr[j] * Rs[j];
+      PRv[0] = v;
+      gw_gather<G, 1>(PRv, gb, Ps);
+#pragma unroll
+      for (int j = 0; j < G; ++j)
+        if (j < d) q += Rs[j] * Ps[j];
+    } else {
+#pragma unroll
+      for (int u = 0; u < V; ++u) {
+        const double v = gw_dotc<1, G, V>(
+            0.0, 0, d, d, [&](int j) { return tg.gprec[kk[u] * d + clampd(j, d)]; }, R, gb);
+        PRv[u] = act[u] ? v : 0.0;
+      }
+      q = gw_dotv<G, V>(0.0, d, R, PRv, gb);
+    }
+    lp += tg.gauss_coef * (-0.5 * q);
+  }
+  lp += use_mlp ? tg.mlp_coef * (double)s.out[c] : pv[c];
+  if (tg.box_penalty) {
+    if (!ib) {
+      double pen[V], dp;
+#pragma unroll
+      for (int u = 0; u < V; ++u) pen[u] = act[u] ? box_pen(tg, i + G * u, x[u], &dp) : 0.0;
+      lp = gw_dotc<-1, G, V>(lp, 0, d, d, [&](int) { return 1.0; }, pen, gb);
+    }
+  } else if (box && !ib) {
+    lp = -INFINITY;
+  }
+  if (valid && i == 0) LPo[c] = lp;
+  double g[V];
+#pragma unroll
+  for (int u = 0; u < V; ++u) g[u] = 0.0;
+  if (grad) {
+    double ptw = 0.0, xtw = 0.0;
+    if (tg.gauss_coef != 0.0 && tg.tw_v >= 0) {
+      ptw = gw_at<G, V>(PRv, gb, tg.tw_v);
+      xtw = gw_at<G, V>(x, gb, tg.tw_u);
+    }
+#pragma unroll
+    for (int u = 0; u < V; ++u) {
+      const int k = i + G * u;
+      double gu = 0.0;
+      if (tg.gauss_coef != 0.0) {
+        gu = -PRv[u];
+        if (tg.tw_v >= 0 && k == tg.tw_u) {
+          const double du = xtw - tg.tw_center;
+          gu += -ptw * 2.0 * tg.tw_beta * du;
+        }
+        gu *= tg.gauss_coef;
+      }
+      const double gt = (double)s.gth[c * d + kk[u]], is = tg.in_invscale[kk[u]];
+      if (act[u]) {
+        gu += use_mlp ? tg.mlp_coef * gt * is : pgr[c * d + k];
+        if (tg.box_penalty && !ib) {
+          double dp;
+          box_pen(tg, k, x[u], &dp);
+          gu -= dp;
+        }
+        GXo(k, c) = gu;
+        g[u] = gu;
+      }
+    }
+  }
+  post(c, i, valid, x, g, lp);
+}
 
 // Target evaluation for a tile.  staged: the caller wrote the emulator inputs and flags
 // (grp_stage).  On the lane-group path, post(c, i, valid, x_i, g_i, log pi) runs in every
@@ -556,6 +961,13 @@ __device__ __forceinline__ void eval_tile(const KArgs& a, char* smem, typename P
   if (tg.plain_mode != 0) {
     for (int c = 0; c < mv; ++c) {
       if (!intrain[c]) plain_chain(tg, X, c, grad, psc, pv + c, pgr + c * d);
+    }
+  }
+  if constexpr (kWide<MT> && IsWidePost<Post>::value) {
+    if (wide_path<P, MT>(a)) {
+      gw_eval<P, MT, 16, 2>(a, s, X, mv, LPo, GXo, grad, box, pv, pgr, inbox, intrain, post);
+      __syncthreads();
+      return;
     }
   }
   if (group_path<P, MT>(a)) {
@@ -887,6 +1299,252 @@ __device__ __forceinline__ void mh_tile(const KArgs& a, char* smem, typename P::
   __syncthreads();
 }
 
+// MALA on wide lane groups (the expressions of the loop form in mala_tile, in their order):
+// whitening, drift and noise and the proposal here; reverse drift, acceptance and commit in
+// the evaluation's continuation.  The chain's tally lives in thread G c.
+template <class P, int MT, int G, int V>
+__device__ __forceinline__ void mala_gw(const KArgs& a, char* smem, typename P::acc* hsave,
+                                         Tally& ty, int64_t c0, int mv, uint64_t t, double eps) {
+  constexpr int M = 16 * MT, N = G * V;
+  const State& S = a.st;
+  const int d = a.tg.d, tid = local_tid();
+  const double* Lw = a.wh.L;
+  const Scratch T = tile_scratch<MT>(a, smem, c0);
+  const TView GX{S.gx + c0, S.Np};
+  const int* inbox = (const int*)(smem + a.lds.mi);
+  const double* mult = a.step_mult;
+  const double sq = sqrt(2.0 * eps);
+  if (tid < G * M) {
+    const int c = tid / G, i = tid % G, gb = gw_base<G>(tid), cc = clampd(c, mv);
+    const bool valid = c < mv;
+    double x[V], gx[V], z[V], gz[V], zp[V], xp[V];
+#pragma unroll
+    for (int u = 0; u < V; ++u) {
+      const int kk = clampd(i + G * u, d);
+      const bool act = valid && i + G * u < d;
+      const double xr = S.x[kk * S.Np + c0 + cc], gr = GX(kk, cc);
+      x[u] = act ? xr : 0.0;
+      gx[u] = act ? gr : 0.0;
+    }
+    gw_whiten<G, V>(a.wh.mu, Lw, d, i, gb, x, z);
+    gw_lt<G, V>(Lw, d, i, gb, gx, gz);
+#pragma unroll
+    for (int u = 0; u < V; ++u) {
+      const int k = i + G * u;
+      zp[u] = 0.0;
+      if (valid && k < d) {
+        const double ei = mult ? eps * mult[k] : eps, sqi = mult ? sqrt(2.0 * ei) : sq;
+        zp[u] = z[u] + ei * gz[u] + sqi * normal_dim(a.rng, c0 + c, t, kStreamNormal, 0, k);
+        T.z(k, c) = z[u];
+        T.gz(k, c) = gz[u];
+        T.zp(k, c) = zp[u];
+      }
+    }
+    gw_affine<G, V>(a.wh.mu, Lw, d, i, gb, zp, xp);
+#pragma unroll
+    for (int u = 0; u < V; ++u)
+      if (valid && i + G * u < d) T.xp(i + G * u, c) = xp[u];
+    gw_stage<P, MT, G, V>(a, smem, c, i, valid, xp);
+  }
+  // eval_tile instantiates both lane-group forms; only the one with this V runs
+  auto post = [&](int c, int i, bool valid, const auto& x, const auto& g, double lp) {
+    if constexpr (sizeof(x) == V * sizeof(double)) {
+    const int gb = gw_base<G>(local_tid()), cc = clampd(c, mv);
+    double gzp[V], df[V], dr[V], ei[V], zr[V], zpr[V], gzr[V];
+    // the scratch loads first: their latency overlaps the permutes of L^T g
+#pragma unroll
+    for (int u = 0; u < V; ++u) {
+      const int kk = clampd(i + G * u, d);
+      zr[u] = T.z(kk, cc);
+      zpr[u] = T.zp(kk, cc);
+      gzr[u] = T.gz(kk, cc);
+      ei[u] = mult ? eps * mult[kk] : eps;
+    }
+    gw_lt<G, V>(Lw, d, i, gb, g, gzp);
+#pragma unroll
+    for (int u = 0; u < V; ++u) {
+      df[u] = dr[u] = 0.0;
+      if (valid && i + G * u < d) {
+        df[u] = zpr[u] - zr[u] - ei[u] * gzr[u];
+        dr[u] = zr[u] - zpr[u] - ei[u] * gzp[u];
+      }
+    }
+    double fwd = 0, rev = 0;
+    if (mult) {
+#pragma unroll
+      for (int jb = 0; jb < N; jb += 8) {
+        if (jb >= d) break;
+        double dfs[8], drs[8], es[8];
+        gw_block<G, V>(df, gb, jb, dfs);
+        gw_block<G, V>(dr, gb, jb, drs);
+        gw_block<G, V>(ei, gb, jb, es);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          if (jb + u < d) {
+            fwd += dfs[u] * dfs[u] / (4.0 * es[u]);
+            rev += drs[u] * drs[u] / (4.0 * es[u]);
+          }
+        }
+      }
+    } else {
+      if constexpr (V == 1) {
+        double dfs[G], drs[G];
+        gw_gather<G, 1>(df, gb, dfs);
+        gw_gather<G, 1>(dr, gb, drs);
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+          if (j < d) {
+            fwd += dfs[j] * dfs[j];
+            rev += drs[j] * drs[j];
+          }
+        }
+      } else {
+        fwd = gw_sumsq<G, V>(0.0, d, df, gb);
+        rev = gw_sumsq<G, V>(0.0, d, dr, gb);
+      }
+      fwd /= 4.0 * eps;
+      rev /= 4.0 * eps;
+    }
+    int acc = 0;
+    if (valid && i == 0) {
+      const int64_t ch = c0 + c;
+      const double la = lp - S.lp[ch] + (-rev) - (-fwd);
+      acc = decide(a, ty, ch, t, 0, la, lp, inbox[c]) ? 1 : 0;
+      if (acc) S.lp[ch] = lp;
+    }
+    acc = __builtin_amdgcn_ds_bpermute(gb, acc);  // chain c's decision, from thread G c
+#pragma unroll
+    for (int u = 0; u < V; ++u) {
+      const int k = i + G * u;
+      if (acc && valid && k < d) {
+        S.x[k * S.Np + c0 + c] = x[u];
+        S.gx[k * S.Np + c0 + c] = g[u];
+      }
+    }
+    }
+  };
+  eval_tile<P, MT>(a, smem, hsave, T.xp, mv, T.lpp, T.gxp, true, true, true,
+                   WidePost<decltype(post)>{post});
+}
+
+// HMC on wide lane groups (the expressions of the loop form in hmc_tile, in their order): start,
+// first half kick and drift and the first proposal here; each evaluation's closing half
+// kick, the next half kick, drift and proposal, or after the last one accept / reject and
+// commit, in the evaluation's continuation.  The chain's tally lives in thread G c.
+template <class P, int MT, int G, int V>
+__device__ __forceinline__ void hmc_gw(const KArgs& a, char* smem, typename P::acc* hsave,
+                                        Tally& ty, int64_t c0, int mv, uint64_t t, double eps) {
+  constexpr int M = 16 * MT, N = G * V;
+  const State& S = a.st;
+  const int d = a.tg.d, tid = local_tid();
+  const double* Lw = a.wh.L;
+  const Scratch T = tile_scratch<MT>(a, smem, c0);
+  const TView GX{S.gx + c0, S.Np};
+  const int* inbox = (const int*)(smem + a.lds.mi);
+  double* h0 = (double*)(smem + a.lds.md);
+  const double he = 0.5 * eps;
+  if (tid < G * M) {
+    const int c = tid / G, i = tid % G, gb = gw_base<G>(tid), cc = clampd(c, mv);
+    const bool valid = c < mv;
+    double x[V], gx[V], z[V], q[V], gz[V], zp[V], xp[V];
+#pragma unroll
+    for (int u = 0; u < V; ++u) {
+      const int k = i + G * u, kk = clampd(k, d);
+      const bool act = valid && k < d;
+      const double xr = S.x[kk * S.Np + c0 + cc], gr = GX(kk, cc);
+      x[u] = act ? xr : 0.0;
+      gx[u] = act ? gr : 0.0;
+    }
+    gw_whiten<G, V>(a.wh.mu, Lw, d, i, gb, x, z);
+#pragma unroll
+    for (int u = 0; u < V; ++u) {
+      const int k = i + G * u;
+      q[u] = (valid && k < d) ? normal_dim(a.rng, c0 + c, t, kStreamNormal, 0, k) : 0.0;
+    }
+    const double ke = gw_sumsq<G, V>(0.0, d, q, gb);
+    gw_lt<G, V>(Lw, d, i, gb, gx, gz);
+    double qh[V];
+#pragma unroll
+    for (int u = 0; u < V; ++u) {
+      qh[u] = q[u] + he * gz[u];
+      zp[u] = z[u] + eps * qh[u];
+    }
+    gw_affine<G, V>(a.wh.mu, Lw, d, i, gb, zp, xp);
+#pragma unroll
+    for (int u = 0; u < V; ++u) {
+      const int k = i + G * u;
+      if (valid && k < d) {
+        T.q(k, c) = qh[u];
+        T.zp(k, c) = zp[u];
+        T.xp(k, c) = xp[u];
+      }
+    }
+    if (valid && i == 0) h0[c] = -S.lp[c0 + c] + 0.5 * ke;
+    gw_stage<P, MT, G, V>(a, smem, c, i, valid, xp);
+  }
+  for (int l = 0; l < a.n_leap; ++l) {
+    const bool last = l + 1 == a.n_leap;
+    // eval_tile instantiates both lane-group forms; only the one with this V runs
+    auto post = [&](int c, int i, bool valid, const auto& x, const auto& g, double lp) {
+      if constexpr (sizeof(x) == V * sizeof(double)) {
+      const int gb = gw_base<G>(local_tid()), cc = clampd(c, mv);
+      double qr[V], zr[V], gz[V], q[V];
+#pragma unroll
+      for (int u = 0; u < V; ++u) {
+        const int kk = clampd(i + G * u, d);
+        qr[u] = T.q(kk, cc);
+        zr[u] = T.zp(kk, cc);
+      }
+      gw_lt<G, V>(Lw, d, i, gb, g, gz);
+#pragma unroll
+      for (int u = 0; u < V; ++u) q[u] = ((valid && i + G * u < d) ? qr[u] : 0.0) + he * gz[u];
+      if (!last) {
+        double zp[V], xp[V];
+#pragma unroll
+        for (int u = 0; u < V; ++u) {
+          const double qh = q[u] + he * gz[u];
+          q[u] = qh;
+          zp[u] = ((valid && i + G * u < d) ? zr[u] : 0.0) + eps * qh;
+        }
+        gw_affine<G, V>(a.wh.mu, Lw, d, i, gb, zp, xp);
+#pragma unroll
+        for (int u = 0; u < V; ++u) {
+          const int k = i + G * u;
+          if (valid && k < d) {
+            T.q(k, c) = q[u];
+            T.zp(k, c) = zp[u];
+            T.xp(k, c) = xp[u];
+          }
+        }
+        gw_stage<P, MT, G, V>(a, smem, c, i, valid, xp);
+        return;
+      }
+      const double ke = gw_sumsq<G, V>(0.0, d, q, gb);
+      int acc = 0;
+      if (valid && i == 0) {
+        const int64_t ch = c0 + c;
+        const double lp1 = (inbox[c] || a.tg.box_penalty) ? lp : -INFINITY;
+        const double h1 = -lp1 + 0.5 * ke;
+        const double la = h0[c] - h1;
+        acc = decide(a, ty, ch, t, 0, la, lp1, inbox[c]) ? 1 : 0;
+        if (acc) S.lp[ch] = lp1;
+      }
+      acc = __builtin_amdgcn_ds_bpermute(gb, acc);  // chain c's decision, from thread G c
+#pragma unroll
+      for (int u = 0; u < V; ++u) {
+        const int k = i + G * u;
+        if (acc && valid && k < d) {
+          S.x[k * S.Np + c0 + c] = x[u];
+          S.gx[k * S.Np + c0 + c] = g[u];
+        }
+      }
+      }
+    };
+    eval_tile<P, MT>(a, smem, hsave, T.xp, mv, T.lpp, T.gxp, true, false, true,
+                     WidePost<decltype(post)>{post});
+  }
+}
+
 template <class P, int MT>
 __device__ __forceinline__ void mala_tile(const KArgs& a, char* smem, typename P::acc* hsave,
                                           Tally& ty, int64_t c0, int mv, uint64_t t, double eps) {
@@ -900,6 +1558,12 @@ __device__ __forceinline__ void mala_tile(const KArgs& a, char* smem, typename P
   int* flag = inbox + 2 * M;
   const double* mult = a.step_mult;  // per-dimension steps eps_i = eps m_i when set
   const double sq = sqrt(2.0 * eps);
+  if constexpr (kWide<MT>) {
+    if (wide_path<P, MT>(a)) {
+      mala_gw<P, MT, 16, 2>(a, smem, hsave, ty, c0, mv, t, eps);
+      return;
+    }
+  }
   if (group_path<P, MT>(a)) {
     // lane groups (the expressions of the loop form below, in their order): whitening,
     // drift and noise and the proposal here; reverse drift, acceptance and commit in the
@@ -1055,6 +1719,12 @@ __device__ __forceinline__ void hmc_tile(const KArgs& a, char* smem, typename P:
   int* flag = inbox + 2 * M;
   double* h0 = (double*)(smem + a.lds.md);
   const double he = 0.5 * eps;
+  if constexpr (kWide<MT>) {
+    if (wide_path<P, MT>(a)) {
+      hmc_gw<P, MT, 16, 2>(a, smem, hsave, ty, c0, mv, t, eps);
+      return;
+    }
+  }
   if (group_path<P, MT>(a)) {
     // lane groups (the expressions of the loop form below, in their order): start, first
     // half kick and drift and the first proposal here; each evaluation's closing half kick,
@@ -1592,8 +2262,13 @@ __global__ __launch_bounds__(kThreads, 1) void step_kernel(KArgs a) {
       if constexpr (!kHalves) record_tile(a, s, a.tg.d, M, mv, c0);
     }
     if constexpr (SAMPLER != 4) {
-      // the lane-group MALA / HMC keep chain c's tally in thread 8c, the others in thread c
-      const int own = ((SAMPLER == 1 || SAMPLER == 2) && group_path<P, MT>(a)) ? 8 : 1;
+      // the lane-group MALA / HMC keep chain c's tally in thread G c (G = 8 or 16), the
+      // others in thread c
+      int own = 1;
+      if constexpr (SAMPLER == 1 || SAMPLER == 2) {
+        if (group_path<P, MT>(a)) own = 8;
+        else if (wide_path<P, MT>(a)) own = 16;
+      }
       const int tid = local_tid();
       if (a.n_steps > 0 && tid % own == 0 && tid / own < mv) flush_tally(a.st, c0 + tid / own, ty);
     }

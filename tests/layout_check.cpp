@@ -96,9 +96,12 @@ static void check_config(int prec, int MT, const Shape& s, int lds_h, int st_lds
   rg.push_back({"up", L.up, L.up + M * va});
   rg.push_back({"mi", L.mi, L.mi + 4 * M * 4});
   rg.push_back({"md", L.md, L.md + 8 * M * 8});
-  if (st_lds) {
+  if (st_lds == 1) {
     CHECK(L.st >= 0 && L.cst >= 0, "st_lds without regions");
     rg.push_back({"st", L.st, L.st + (7 * d * M + M) * 8});
+    rg.push_back({"cst", L.cst, L.cst + (2 * d * d + 8 * d) * 8});
+  } else if (st_lds == 2) {  // the launch constants alone
+    CHECK(L.st < 0 && L.cst >= 0, "constants-only layout");
     rg.push_back({"cst", L.cst, L.cst + (2 * d * d + 8 * d) * 8});
   } else {
     CHECK(L.st < 0 && L.cst < 0, "regions without st_lds");
@@ -180,7 +183,7 @@ static void check_prec(int prec, const std::vector<Shape>& shapes) {
           "w1t bytes");
     for (int MT = 1; MT <= mt_max(prec); MT *= 2)
       for (int lds_h = 0; lds_h <= 1; ++lds_h)
-        for (int st = 0; st <= 1; ++st)
+        for (int st = 0; st <= 2; ++st)
           for (int w1 = 0; w1 <= 1; ++w1) check_config<P>(prec, MT, s, lds_h, st, w1);
   }
 }

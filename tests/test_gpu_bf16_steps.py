@@ -131,3 +131,42 @@ def test_half_precision_step_against_replay_and_oracle(prec, sampler):
         assert bad_or.mean() < 0.01
         assert 0.3 < info["accepted"].mean() <= 1.0
     ctx.close()
+
+
+@pytest.mark.parametrize("d", [12, 27])
+@pytest.mark.parametrize("sampler", ["mala", "hmc"])
+def test_wide_lane_groups_against_replay(d, sampler):
+    """BF16 on 32-chain tiles with 8 < d <= 32 runs the wide lane-group form of the FP64
+    work (sixteen threads per chain, components i and i + 16 in thread i).  The fused
+    transition is checked against the host replay on the library's own evaluations, as in
+    comparison 1 above; 262 chains leave a ragged last tile."""
+    from workloads import small_problem
+    prob = small_problem(d=d, width=128, n_hidden=3)
+    n = 262
+    ctx = B.best_init(prob, n_chains=n, precision="bf16", seed=SEED, chains_per_block=32)
+    L = np.linalg.cholesky(prob["closed_cov"])
+    B.best_set_whitening(ctx, prob["gauss_mean"], L)
+    xi = np.random.default_rng(SEED + d).normal(size=(n, d))
+    B.best_set_state(ctx, (prob["gauss_mean"] + 0.5 * xi @ L.T).T.copy())
+    eps, n_leap = (0.15, 1) if sampler == "mala" else (0.1, 5)
+    mu, Lw = B.best_get_whitening(ctx)
+    W = dict(mu=mu, L=Lw)
+    accepted = 0
+    for _ in range(2):
+        t = B.best_get_step_counter(ctx)
+        x0, lp0, g0 = B.best_get_state(ctx)
+        x0, g0 = x0.T.copy(), g0.T.copy()
+        if sampler == "mala":
+            x_rp, acc_rp, la_rp, lu = _replay_mala(ctx, W, x0, lp0, g0, t, eps)
+            B.best_step(ctx, "mala", 1, eps=eps)
+        else:
+            x_rp, acc_rp, la_rp, lu = _replay_hmc(ctx, prob, W, x0, lp0, g0, t, eps, n_leap)
+            B.best_step(ctx, "hmc", 1, eps=eps, n_leapfrog=n_leap)
+        x1 = B.best_get_state(ctx)[0].T
+        acc_gpu = np.any(x1 != x0, axis=1)
+        bad = acc_gpu != acc_rp
+        assert np.all(np.abs(la_rp - lu)[bad] < 1e-6), np.abs(la_rp - lu)[bad]
+        assert _rel(x1[~bad], x_rp[~bad], x0[~bad]).max() < 1e-6
+        accepted += int(acc_gpu.sum())
+    assert accepted > 0.1 * 2 * n, accepted
+    ctx.close()
