@@ -133,13 +133,14 @@ def test_half_precision_step_against_replay_and_oracle(prec, sampler):
     ctx.close()
 
 
-@pytest.mark.parametrize("d", [12, 27])
+@pytest.mark.parametrize("d", [12, 17, 27, 32])
 @pytest.mark.parametrize("sampler", ["mala", "hmc"])
 def test_wide_lane_groups_against_replay(d, sampler):
     """BF16 on 32-chain tiles with 8 < d <= 32 runs the wide lane-group form of the FP64
     work (sixteen threads per chain, components i and i + 16 in thread i).  The fused
     transition is checked against the host replay on the library's own evaluations, as in
-    comparison 1 above; 262 chains leave a ragged last tile."""
+    comparison 1 above; 262 chains leave a ragged last tile.  d = 17 leaves one second
+    component (thread 0's), d = 32 fills every slot of both halves."""
     from workloads import small_problem
     prob = small_problem(d=d, width=128, n_hidden=3)
     n = 262
