@@ -142,7 +142,19 @@ def test_wide_lane_groups_against_replay(d, sampler):
     comparison 1 above; 262 chains leave a ragged last tile.  d = 17 leaves one second
     component (thread 0's), d = 32 fills every slot of both halves."""
     from workloads import small_problem
-    prob = small_problem(d=d, width=128, n_hidden=3)
+    _wide_replay(small_problem(d=d, width=128, n_hidden=3), sampler)
+
+
+@pytest.mark.parametrize("sampler", ["mala", "hmc"])
+def test_wide_lane_groups_on_the_27_parameter_network(sampler):
+    """The same check on the 27-parameter workload's network (27 -> 1024 x 5 -> 1) at
+    32-chain tiles: its two 64 KiB activation buffers leave LDS room for the launch
+    constants only, so the tile scratch of the wide form lives in global memory."""
+    _wide_replay(make_problem("c5"), sampler)
+
+
+def _wide_replay(prob, sampler):
+    d = prob["d"]
     n = 262
     ctx = B.best_init(prob, n_chains=n, precision="bf16", seed=SEED, chains_per_block=32)
     L = np.linalg.cholesky(prob["closed_cov"])
@@ -170,4 +182,18 @@ def test_wide_lane_groups_against_replay(d, sampler):
         assert _rel(x1[~bad], x_rp[~bad], x0[~bad]).max() < 1e-6
         accepted += int(acc_gpu.sum())
     assert accepted > 0.1 * 2 * n, accepted
+    # three steps in one launch end bitwise where three one-step launches end (the tile
+    # scratch carries nothing from one step to the next)
+    x_mid, lp_mid, g_mid = B.best_get_state(ctx)
+    t_mid = B.best_get_step_counter(ctx)
+    kw = dict(eps=eps) if sampler == "mala" else dict(eps=eps, n_leapfrog=n_leap)
+    ends = []
+    for split in ((3,), (1, 1, 1)):
+        B.best_set_state(ctx, x_mid, lp_mid, g_mid)
+        B.best_set_step_counter(ctx, t_mid)
+        for k in split:
+            B.best_step(ctx, sampler, k, **kw)
+        ends.append(B.best_get_state(ctx))
+    for a, b in zip(*ends):
+        assert np.array_equal(a, b)
     ctx.close()
