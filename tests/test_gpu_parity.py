@@ -259,6 +259,34 @@ def test_resume_from_checkpoint_is_bitwise():
     assert np.array_equal(B.best_get_state(c)[0], xa)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("d", [5, 12])
+@pytest.mark.parametrize("sampler,kw", [
+    ("mh", dict(mh_scale=0.8)), ("mala", dict(eps=0.2)), ("hmc", dict(eps=0.1, n_leapfrog=4)),
+    ("nuts", dict(eps=0.2, max_depth=5)), ("aies", {}), ("de", {})])
+def test_launch_split_is_bitwise(prec, d, sampler, kw):
+    """Four transitions as one launch, as 1 + 3 and as 2 + 1 + 1 end in the same state, bit
+    for bit: each step's randomness is keyed by its counter and nothing but the chain state
+    passes from one step to the next (d = 5: lane groups of eight; d = 12: the loop form)."""
+    prob = small_problem(d=d, width=128, n_hidden=2)
+    ends, counters = [], []
+    for split in ((4,), (1, 3), (2, 1, 1)):
+        ctx = B.best_init(prob, n_chains=96, precision=prec, seed=6, init="gaussian",
+                          init_point=prob["gauss_mean"], init_scale=0.1)
+        B.best_set_whitening(ctx, prob["gauss_mean"], np.linalg.cholesky(prob["closed_cov"]))
+        x_init = B.best_get_state(ctx)[0]
+        for k in split:
+            B.best_step(ctx, sampler, k, **kw)
+        ends.append(B.best_get_state(ctx))
+        counters.append(B.best_get_step_counter(ctx))
+        ctx.close()
+    assert counters[0] == counters[1] == counters[2]
+    assert np.mean(np.any(ends[0][0] != x_init, axis=0)) > 0.2   # the chains moved
+    for e in ends[1:]:
+        for a, b in zip(ends[0], e):
+            assert np.array_equal(a, b)
+
+
 def test_fp64_gradient_samplers_are_refused():
     prob = small_problem(d=4, width=128, n_hidden=2)
     ctx = B.best_init(prob, n_chains=32, precision="fp64", seed=1)
