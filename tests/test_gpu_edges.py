@@ -66,6 +66,38 @@ def test_empty_and_zero_step_calls():
     assert np.array_equal(B.best_get_state(ctx)[0], x0)
 
 
+@pytest.mark.parametrize("sampler,kw", [("mala", dict(eps=0.2)),
+                                        ("mala", dict(eps=0.2, adapt_eps=True)),
+                                        ("hmc", dict(eps=0.1, n_leapfrog=3)),
+                                        ("nuts", dict(eps=0.2, max_depth=4)),
+                                        ("aies", {})])
+def test_record_thinning_and_capacity(sampler, kw):
+    """Slot k of a call's record holds the state after step (k + 1) thin, as float32 of x;
+    a record shorter than the call keeps its first slots and the memory past it is not
+    touched; recording does not change the chains.  With adapt_eps every step is a launch
+    of its own, so the slot index crosses launches; AIES records after both half-moves."""
+    prob = small_problem(d=5, width=128, n_hidden=2)
+    n, steps, d = 64, 9, prob["d"]
+
+    def run(thin, cap, slots):
+        ctx = B.best_init(prob, n_chains=n, precision="fp32", seed=8, init="gaussian",
+                          init_point=prob["gauss_mean"], init_scale=0.1)
+        B.best_set_whitening(ctx, prob["gauss_mean"], np.linalg.cholesky(prob["closed_cov"]))
+        buf = torch.full((slots, d, n), float("nan"), dtype=torch.float32, device="cuda")
+        B.best_step(ctx, sampler, steps, thin=thin, record=buf[:cap], **kw)
+        x = B.best_get_state(ctx)[0]
+        ctx.close()
+        return buf.cpu().numpy(), x
+
+    every, x_every = run(1, steps, steps)
+    thinned, x_thin = run(3, 2, 4)
+    assert np.array_equal(x_every, x_thin)
+    assert np.array_equal(every[-1], x_every.astype(np.float32))
+    assert np.array_equal(thinned[0], every[2]) and np.array_equal(thinned[1], every[5])
+    assert np.all(np.isnan(thinned[2:]))          # past the capacity: untouched
+    assert np.mean(np.any(every[-1] != every[0], axis=0)) > 0.2   # the chains moved
+
+
 def _one_step_oracle(prob, ctx, sampler, kw, seed):
     """Oracle transition from the GPU's current state (same Philox streams)."""
     t = B.best_get_step_counter(ctx)
