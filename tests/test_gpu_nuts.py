@@ -66,6 +66,15 @@ def test_lockstep_depth_limit_reached():
     assert np.all(depths == 4)
 
 
+def test_lockstep_at_the_largest_depth():
+    """The largest supported depth (12): a step too small to turn builds every tree to 4095
+    leaves, with a pending sibling at every one of the twelve levels; 8 chains in one
+    ragged tile."""
+    prob = small_problem(d=3, width=128, n_hidden=2, seed=21)
+    depths = _lockstep_nuts(prob, 8, 1e-4, B.BEST_NUTS_MAX_DEPTH, steps=1, seed=0xBE63)
+    assert B.BEST_NUTS_MAX_DEPTH == 12 and np.all(depths == 12)
+
+
 @pytest.mark.parametrize("cpb", [64, 16])
 def test_lockstep_27_parameters_wide_tiles(cpb):
     """d = 27 (lane groups of 32 lanes per chain, 5 of them idle) in 64- and 16-chain tiles."""
