@@ -130,6 +130,10 @@ def test_gaussian_posterior_recovery_bf16():
 
 
 def test_dual_averaging_reaches_target_statistic():
+    """After 200 adaptation steps and finalising to the averaged iterate, the NUTS
+    acceptance statistic over 60 steps x 2048 chains is within 0.03 of the target, the bar
+    of the MALA / HMC dual-averaging test (measured offsets -0.0025 .. +0.0013 over three
+    seeds, Monte-Carlo error of the mean about 0.001)."""
     prob = make_problem("c2")
     n = 2048
     ctx = B.best_init(prob, n_chains=n, precision="bf16", seed=3, init="gaussian",
@@ -140,7 +144,7 @@ def test_dual_averaging_reaches_target_statistic():
     B.best_adapt(ctx, update_mean=False, finalize_da=True)
     st = B.best_step(ctx, "nuts", 60, max_depth=6)
     stat = st["sum_accept_prob"] / (60 * n)
-    assert abs(stat - 0.8) < 0.08, (stat, st["eps"])
+    assert abs(stat - 0.8) < 0.03, (stat, st["eps"])
 
 
 def test_nuts_arguments_are_validated():
