@@ -22,7 +22,8 @@ def trained():
 
 def test_training_loss_falls(trained):
     _, tr = trained
-    assert tr["losses"][-1] < 0.01 * tr["losses"][0], tr["losses"][::5]
+    # measured: the last epoch's loss is 1.2e-4 of the first
+    assert tr["losses"][-1] < 2e-3 * tr["losses"][0], tr["losses"][::5]
 
 
 def test_emulator_matches_plain_model_near_the_mode(trained):
@@ -36,8 +37,9 @@ def test_emulator_matches_plain_model_near_the_mode(trained):
     lo, _ = OT.plain_logL(prob["plain"], x)
     err = lp - lo
     # a constant offset cancels in sampling; the spread is what matters.  With this test's
-    # training budget (32768 pairs, 40 epochs) the emulator captures most of the variation.
-    assert np.std(err) < 0.25 * np.std(lo) + 1.0, (np.std(err), np.std(lo))
+    # training budget (32768 pairs, 40 epochs) the emulator captures most of the variation:
+    # measured, the error's spread is 0.14 of the plain log-likelihood's (1.8 against 13.1)
+    assert np.std(err) < 0.2 * np.std(lo), (np.std(err), np.std(lo))
 
 
 def test_sampling_the_emulator_with_importance_weights_and_gain(trained):
