@@ -65,6 +65,9 @@ def test_sampling_the_emulator_with_importance_weights_and_gain(trained):
     le, _ = B.best_logL_grad(ctx_e, xs, want_grad=False)
     w, kish = B.best_importance_weights(lp, le)
     frac = kish / xs.shape[1]
-    assert frac > 0.05, frac
-    assert res["emulator"]["accept"] > 0.2 and res["plain"]["accept"] > 0.2
-    assert res["emulator"]["evals_per_s"] > res["plain"]["evals_per_s"], res
+    # measured: Kish fraction 0.46; acceptance 0.57 for both (the dual-averaging target);
+    # the emulator 19x the plain model's evals/s and min-ESS/s at about the same min-ESS
+    assert frac > 0.25, frac
+    assert abs(res["emulator"]["accept"] - 0.57) < 0.1 and abs(res["plain"]["accept"] - 0.57) < 0.1
+    assert res["emulator"]["evals_per_s"] > 5 * res["plain"]["evals_per_s"], res
+    assert res["emulator"]["min_ess_per_s"] > 5 * res["plain"]["min_ess_per_s"], res
